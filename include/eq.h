@@ -1,0 +1,148 @@
+/*
+ * eq.h -- C ABI of libeq: equilibrium projection of voxelized symmetric stress
+ * fields on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Zhou, Lebensohn, Reischig, Ludwig, Bhattacharya, "Imposing
+ * equilibrium on measured 3-D stress fields using Hodge decomposition and
+ * FFT-based optimization"):
+ *
+ *   S_equil = argmin { ||S - S_exp||_2 : S periodic, symmetric, div S = 0 }
+ *                                         (Section 3.2, problem statement)
+ *
+ * solved in Fourier space (Section 3.3 solution strategy, Section 4): the mean
+ * c0 of S_exp is kept, and at every frequency q with a nonzero derivative
+ * symbol s(q) the spectrum A(q) (a complex symmetric 3x3 matrix) is replaced by
+ * curl H curl with nabla^4 H = curl A curl (eqnELH, eq:sequil), which equals
+ * P A P with P = I - n n^T, n = s/|s|.  Frequencies whose symbol vanishes (the
+ * mean and the 7 Nyquist corners of an even grid) are divergence-free under
+ * the discrete operator and are kept unchanged.  The removed part
+ * S_exp - S_equil is the symmetrized gradient of Theorem 2.
+ *
+ * Two derivative symbols (Section 4):
+ *   EQ_OP_CDO  continuous:  xi(q) = 2 pi k(q) / (n h), k = q (q < n/2),
+ *              0 (q = n/2), q - n (q > n/2)                      (eq:cdo)
+ *   EQ_OP_DDO  central difference (the paper's operator for interfaces):
+ *              s(q) = sin(2 pi q / n) / h                        (eq:diff)
+ *
+ * Data conventions (every entry point):
+ *   - a field is C-contiguous (6, nz, ny, nx), x fastest; a batch is
+ *     (batch, 6, nz, ny, nx); components in Voigt order (11, 22, 33, 23, 13, 12)
+ *     with tensor index 1 = x, 2 = y, 3 = z;
+ *   - element type is double (EQ_FP64) or float (EQ_FP32) per eq_desc.prec;
+ *   - all field buffers are caller-owned DEVICE pointers on the plan's device;
+ *     the library never frees or retains them beyond a call (except the
+ *     graph cache of EQ_F_CAPTURE_GRAPH, which remembers their addresses);
+ *   - the norm is Frobenius: off-diagonal Voigt components weigh 2.
+ *
+ * Errors: every call returns an eq_status; nothing aborts or throws across the
+ * ABI.  eq_last_error() returns a thread-local message for the last failure.
+ * Argument checks happen on the host before any device work is enqueued.
+ */
+#ifndef EQ_H
+#define EQ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eq_plan_s* eq_plan_t;   /* opaque; from eq_plan, freed by eq_plan_destroy */
+
+typedef enum {
+  EQ_OK = 0,
+  EQ_ERR_ARG = 1,        /* null/aliased pointer, bad enum, bad h, batch < 1, bad flags */
+  EQ_ERR_SIZE = 2,       /* a grid edge is odd, < 4, > 1024, or has a prime factor > 5; or
+                            nx / (largest of 8, 4, 2 dividing nx) > 170; or LDS beyond the device limit */
+  EQ_ERR_NOMEM = 3,      /* device allocation failed (or EQ_FAULT_INJECT=alloc) */
+  EQ_ERR_DEVICE = 4,     /* a HIP runtime call failed; see eq_last_error() */
+  EQ_ERR_NONFINITE = 5   /* EQ_F_CHECK_FINITE: the input holds a NaN or Inf */
+} eq_status;
+
+typedef enum { EQ_OP_CDO = 0, EQ_OP_DDO = 1 } eq_op;
+/* EQ_FP32: float data and FFT arithmetic; twiddles and symbols are generated in
+ * FP64 on the device, and the per-frequency normalization 1/|s| is formed in FP64. */
+typedef enum { EQ_FP64 = 0, EQ_FP32 = 1 } eq_prec;
+
+enum {
+  EQ_F_CHECK_FINITE = 1u,   /* eq_project scans the input and synchronizes; NaN/Inf -> EQ_ERR_NONFINITE */
+  EQ_F_CAPTURE_GRAPH = 2u,  /* eq_project records its launches once per (s_in, s_eq, s_removed) and
+                               replays a hipGraph afterwards; needs a stream other than the null stream */
+  EQ_F_PERSISTENT = 4u,     /* reserved: a single persistent launch for the whole batch (rejected for now) */
+  EQ_F_OWN_STREAM = 8u      /* the plan creates and owns a non-blocking stream; hip_stream is ignored */
+};
+
+typedef struct {
+  int nx, ny, nz;      /* grid edges: even, 4..1024, prime factors in {2, 3, 5} (Section 4: N even) */
+  int batch;           /* independent fields of identical shape, >= 1 */
+  int op;              /* eq_op */
+  int prec;            /* eq_prec */
+  double h;            /* voxel spacing, finite and > 0; L = n h.  The projection itself does not
+                          depend on h (only the direction of s matters); residual norms do. */
+  unsigned flags;      /* EQ_F_* */
+} eq_desc;
+
+/* Create a plan: validates *d on the host, allocates the device workspace
+ * (the Hermitian half spectrum, batch * 6 * (nz/2+1) * ny * nx complex values),
+ * and launches the FP64 table kernel (twiddles, symbols) once.
+ * hip_stream: the hipStream_t to enqueue on; NULL is HIP's null stream.  With
+ * EQ_F_OWN_STREAM the plan creates its own non-blocking stream instead.
+ * The plan binds to the device current at this call.  Not thread-safe: one
+ * plan per thread at a time; distinct plans may run concurrently. */
+eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out);
+
+/* Equilibrate: s_eq = S_equil(s_in); s_removed (nullable) = s_in - s_eq.
+ * Buffers: device, (batch, 6, nz, ny, nx) of the plan's element type.
+ * s_eq == s_in (in place) is allowed; s_removed must not overlap either.
+ * Stream-ordered and asynchronous (except with EQ_F_CHECK_FINITE). */
+eq_status eq_project(eq_plan_t p, const void* s_in, void* s_eq, void* s_removed);
+
+/* Divergence residual r_i = sum_j D_j S_ij of a field under the plan's operator
+ * (Section 5 divergence maps).  DDO uses real-space central differences (exactly
+ * the DDO symbol); CDO uses the spectral symbol.  Accumulation in FP64.
+ * norms_host: HOST array [batch][3] = { l2 = sqrt(sum_x |r|^2),
+ *   max = max_x |r(x)|, rel = l2 / (max_q |s(q)| * ||s - mean(s)||_F) }.
+ * div_out (nullable): DEVICE (batch, 3, nz, ny, nx) of the element type.
+ * Blocks until norms_host is written. */
+eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_out);
+
+eq_status eq_plan_destroy(eq_plan_t p);
+
+/* Device bytes a plan for *d allocates (workspace + tables + reduction scratch),
+ * for admission control; host only, no device call. */
+eq_status eq_plan_footprint(const eq_desc* d, size_t* bytes);
+
+const char* eq_status_str(eq_status s);
+const char* eq_last_error(void);
+
+/* Rebind the plan to another stream (NULL = the null stream); drops cached graphs. */
+eq_status eq_plan_set_stream(eq_plan_t p, void* hip_stream);
+
+/* Per-pass instrumentation.  When enabled, every kernel of eq_project/eq_residual is
+ * bracketed by hipEvents on the plan stream; eq_plan_pass_stats synchronizes and
+ * reports, per pass i < *count: name, launches, summed milliseconds and the
+ * algorithmic bytes (compulsory reads + writes) of one launch.  Graph replay is
+ * bypassed while enabled. */
+eq_status eq_plan_set_timing(eq_plan_t p, int enable);
+eq_status eq_plan_pass_stats(eq_plan_t p, int max, int* count, const char** names,
+                             long long* launches, double* total_ms, double* bytes_per_launch);
+eq_status eq_plan_reset_stats(eq_plan_t p);
+
+/* Test hooks (same kernels as eq_project, exposed for per-stage parity):
+ * eq_debug_forward: spec_out (device) = the unnormalized forward DFT of s_in as
+ *   complex (re, im) pairs laid out (batch, 6, nz/2+1, ny, nx) -- the half spectrum
+ *   along z, full along y and x.
+ * eq_debug_project_spectrum: in place on such a half spectrum, apply the
+ *   per-frequency projection (forward and inverse x transforms around it are
+ *   skipped). */
+eq_status eq_debug_forward(eq_plan_t p, const void* s_in, void* spec_out);
+eq_status eq_debug_project_spectrum(eq_plan_t p, void* spec_inout);
+
+/* Library build string. */
+const char* eq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EQ_H */

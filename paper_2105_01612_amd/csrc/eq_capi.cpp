@@ -1,0 +1,621 @@
+// eq_capi.cpp -- plan object and C ABI of libeq (declared in include/eq.h).
+//
+// Host-side responsibilities: argument validation before any device work,
+// radix schedules per axis, device workspace and FP64 tables, stream binding,
+// the pass sequence of eq_project / eq_residual, optional hipGraph replay,
+// per-pass event timing, and status codes (nothing aborts or throws across
+// the ABI).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "eq.h"
+#include "eq_internal.hpp"
+
+using namespace eq;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+eq_status fail(eq_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+eq_status hip_fail(hipError_t e, const char* what) {
+  return fail(EQ_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define EQ_HIP(call, what)                         \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+bool fault_inject_alloc() {
+  const char* v = std::getenv("EQ_FAULT_INJECT");
+  return v && std::strcmp(v, "alloc") == 0;
+}
+
+// Radix schedule: 8s first, then one 4 (or 4,4 / 2 to finish the power of two), then 3s and 5s.
+bool factor_axis(int n, AxisFft* out) {
+  if (n < 4 || n > 1024 || (n & 1)) return false;
+  int m = n, a = 0, b = 0, c = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  while (m % 3 == 0) { m /= 3; ++b; }
+  while (m % 5 == 0) { m /= 5; ++c; }
+  if (m != 1) return false;
+  FftDesc d{};
+  d.n = n;
+  int k = 0;
+  int q = a / 3, r = a % 3;
+  if (r == 1 && q >= 1) { q -= 1; r = 4; }     // 2^(3q+1) = 8^(q-1) * 4 * 4
+  for (int i = 0; i < q; ++i) d.r[k++] = 8;
+  if (r == 4) { d.r[k++] = 4; d.r[k++] = 4; }
+  else if (r == 2) d.r[k++] = 4;
+  else if (r == 1) d.r[k++] = 2;
+  for (int i = 0; i < b; ++i) d.r[k++] = 3;
+  for (int i = 0; i < c; ++i) d.r[k++] = 5;
+  if (k > kMaxStages) return false;
+  d.nst = k;
+  out->d = d;
+  out->E = (n % 8 == 0) ? 8 : ((n % 4 == 0) ? 4 : 2);
+  return true;
+}
+
+eq_status validate(const eq_desc* d) {
+  if (!d) return fail(EQ_ERR_ARG, "null descriptor");
+  if (d->batch < 1) return fail(EQ_ERR_ARG, "batch must be >= 1");
+  if (d->op != EQ_OP_CDO && d->op != EQ_OP_DDO) return fail(EQ_ERR_ARG, "op must be EQ_OP_CDO or EQ_OP_DDO");
+  if (d->prec != EQ_FP64 && d->prec != EQ_FP32) return fail(EQ_ERR_ARG, "prec must be EQ_FP64 or EQ_FP32");
+  if (!std::isfinite(d->h) || !(d->h > 0.0)) return fail(EQ_ERR_ARG, "h must be finite and > 0");
+  if (d->flags & ~(unsigned)(EQ_F_CHECK_FINITE | EQ_F_CAPTURE_GRAPH | EQ_F_OWN_STREAM))
+    return fail(EQ_ERR_ARG, "unknown or unsupported flag bits");
+  AxisFft t;
+  const int dims[3] = {d->nx, d->ny, d->nz};
+  const char* names[3] = {"nx", "ny", "nz"};
+  for (int i = 0; i < 3; ++i)
+    if (!factor_axis(dims[i], &t))
+      return fail(EQ_ERR_SIZE, std::string(names[i]) + " = " + std::to_string(dims[i]) +
+                                   ": grid edges must be even, in [4, 1024], with prime factors in {2, 3, 5}");
+  // the fused x pass runs the six component lines of a row in one workgroup
+  factor_axis(d->nx, &t);
+  if (6 * (d->nx / t.E) > 1024)
+    return fail(EQ_ERR_SIZE, "nx = " + std::to_string(d->nx) +
+                                 ": six x-lines need more than 1024 threads (nx / largest of 8, 4, 2 dividing it > 170)");
+  // total element count must be addressable by the launch grids
+  const double rows = (double)d->batch * (d->nz / 2 + 1) * d->ny;
+  if (rows > 2.0e9) return fail(EQ_ERR_SIZE, "batch * (nz/2+1) * ny too large for one launch");
+  return EQ_OK;
+}
+
+size_t elem_size(const eq_desc* d) { return d->prec == EQ_FP64 ? sizeof(double) : sizeof(float); }
+
+constexpr int kRedBlocks = 512;   // reduction partial blocks per field
+
+struct Layout {
+  size_t w_bytes, sym_bytes, tw64_bytes, tw32_bytes, part_bytes, red_bytes, flag_bytes;
+  size_t total() const { return w_bytes + sym_bytes + tw64_bytes + tw32_bytes + part_bytes + red_bytes + flag_bytes; }
+};
+
+Layout layout_of(const eq_desc* d) {
+  Layout L{};
+  const size_t nzh = (size_t)d->nz / 2 + 1;
+  L.w_bytes = (size_t)d->batch * 6 * nzh * d->ny * d->nx * 2 * elem_size(d);
+  const size_t ntab = (size_t)d->nx + d->ny + d->nz;
+  L.sym_bytes = ntab * sizeof(double);
+  L.tw64_bytes = ntab * sizeof(double2);
+  L.tw32_bytes = ntab * sizeof(float2);
+  L.part_bytes = (size_t)d->batch * kRedBlocks * kRedWidth * sizeof(double);
+  L.red_bytes = (size_t)d->batch * kRedWidth * sizeof(double);
+  L.flag_bytes = 256;
+  return L;
+}
+
+enum PassId {
+  P_Z_R2C = 0, P_Y_FWD, P_X_PROJ, P_Y_INV, P_Z_C2R, P_DIV_DDO, P_X_DIV, P_Y_INV3, P_Z_C2R3, P_DIV_STATS,
+  P_REDUCE, P_CHECK, P_X_FWD, P_PROJ_ONLY, P_COUNT
+};
+const char* kPassNames[P_COUNT] = {
+  "z_r2c", "y_fwd", "x_proj", "y_inv", "z_c2r", "div_ddo", "x_div", "y_inv3", "z_c2r3", "div_stats",
+  "reduce_final", "check_finite", "x_fwd", "proj_only"};
+
+struct TimingRec { int pass; hipEvent_t a, b; };
+
+}  // namespace
+
+struct eq_plan_s {
+  eq_desc desc{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Geom g{};
+  AxisFft ax{}, ay{}, az{};
+  Tune tune{};
+  void* W = nullptr;
+  double* sym = nullptr;
+  double2* tw64 = nullptr;
+  float2* tw32 = nullptr;
+  double* partials = nullptr;
+  double* red = nullptr;
+  int* flag = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<TimingRec> pending;
+  std::vector<hipEvent_t> event_pool;
+  long long launches[P_COUNT] = {};
+  double total_ms[P_COUNT] = {};
+  // graph cache
+  struct GraphEntry { const void* in; void* eq; void* rem; hipGraph_t graph; hipGraphExec_t exec; };
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+size_t spectrum_plane_elems(const eq_plan_s* p) { return (size_t)p->g.nzh * p->g.ny * p->g.nx; }
+size_t field_elems(const eq_plan_s* p) { return (size_t)p->g.nz * p->g.ny * p->g.nx; }
+
+double pass_bytes(const eq_plan_s* p, int pass) {
+  const double es = (double)elem_size(&p->desc);
+  const double B = p->g.batch;
+  const double M = (double)field_elems(p);
+  const double Q = (double)spectrum_plane_elems(p) * 2 * es;   // bytes of one component's half spectrum
+  switch (pass) {
+    case P_Z_R2C: return B * 6 * (M * es + Q);
+    case P_Y_FWD: case P_X_PROJ: case P_Y_INV: case P_X_FWD: case P_PROJ_ONLY: return B * 6 * 2 * Q;
+    case P_Z_C2R: return B * 6 * (Q + M * es);
+    case P_DIV_DDO: return B * 6 * M * es;
+    case P_X_DIV: return B * (6 * Q + 3 * Q);
+    case P_Y_INV3: return B * 3 * 2 * Q;
+    case P_Z_C2R3: return B * 3 * (Q + M * es);
+    case P_DIV_STATS: return B * 9 * M * es;
+    case P_CHECK: return B * 6 * M * es;
+    default: return 0.0;
+  }
+}
+
+hipEvent_t get_event(eq_plan_s* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket one launch with events when timing is on.
+template <typename F>
+hipError_t timed(eq_plan_s* p, int pass, F&& launch) {
+  if (!p->timing) return launch();
+  hipEvent_t a = get_event(p), b = get_event(p);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, p->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, p->stream);
+  if (e != hipSuccess) return e;
+  p->pending.push_back({pass, a, b});
+  if (p->pending.size() > 4096) {     // bound the backlog: fold completed records
+    (void)hipEventSynchronize(b);
+    for (auto& r : p->pending) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, r.a, r.b);
+      p->total_ms[r.pass] += ms;
+      p->launches[r.pass] += 1;
+      p->event_pool.push_back(r.a);
+      p->event_pool.push_back(r.b);
+    }
+    p->pending.clear();
+  }
+  return hipSuccess;
+}
+
+void drop_graphs(eq_plan_s* p) {
+  for (auto& ge : p->graphs) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    if (ge.graph) (void)hipGraphDestroy(ge.graph);
+  }
+  p->graphs.clear();
+}
+
+void release(eq_plan_s* p) {
+  if (!p) return;
+  drop_graphs(p);
+  for (auto& r : p->pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto e : p->event_pool) (void)hipEventDestroy(e);
+  if (p->W) (void)hipFree(p->W);
+  if (p->sym) (void)hipFree(p->sym);
+  if (p->tw64) (void)hipFree(p->tw64);
+  if (p->tw32) (void)hipFree(p->tw32);
+  if (p->partials) (void)hipFree(p->partials);
+  if (p->red) (void)hipFree(p->red);
+  if (p->flag) (void)hipFree(p->flag);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+eq_status dev_alloc(void** ptr, size_t bytes, const char* what) {
+  if (fault_inject_alloc()) return fail(EQ_ERR_NOMEM, std::string("injected allocation failure: ") + what);
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(EQ_ERR_NOMEM, std::string("hipMalloc(") + what + ", " + std::to_string(bytes) + " B): " +
+                                  hipGetErrorString(e));
+  }
+  return EQ_OK;
+}
+
+// LDS each pass needs, against the device limit.
+eq_status check_lds(const eq_plan_s* p) {
+  int limit = 0;
+  EQ_HIP(hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device), "hipDeviceGetAttribute");
+  const int eb = 2 * (int)elem_size(&p->desc);
+  const size_t ly = (size_t)pick_tx_y(p->g, p->ay, eb, p->tune) * p->g.ny * eb;
+  const size_t lz = (size_t)(pick_tx_z(p->g, p->az, eb, p->tune) / 2) * p->g.nz * eb;
+  const size_t lx = (size_t)6 * pick_rw_x(p->g, p->ax, eb, p->tune) * (p->g.nx + 1) * eb;
+  const size_t need = std::max(ly, std::max(lz, lx));
+  if (need > (size_t)limit)
+    return fail(EQ_ERR_SIZE, "grid needs " + std::to_string(need) + " B of LDS per workgroup; device allows " +
+                                 std::to_string(limit));
+  return EQ_OK;
+}
+
+template <typename T>
+eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_removed) {
+  using C = cplx<T>;
+  C* W = static_cast<C*>(p->W);
+  const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
+  const C* twx = tw;
+  const C* twy = tw + p->g.nx;
+  const C* twz = tw + p->g.nx + p->g.ny;
+  const Geom& g = p->g;
+  hipStream_t s = p->stream;
+  const size_t M = field_elems(p);
+  EQ_HIP(timed(p, P_Z_R2C, [&] { return launch_z_r2c<T>(static_cast<const T*>(s_in), W, g, p->az, twz, p->tune, s); }),
+         "z_r2c launch");
+  EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, 6, p->ay, twy, false, p->tune, s); }), "y_fwd launch");
+  EQ_HIP(timed(p, P_X_PROJ, [&] { return launch_x<T>(W, g, XM_FWD | XM_PROJ | XM_INV, p->ax, twx, p->sym, p->tune, s); }),
+         "x_proj launch");
+  EQ_HIP(timed(p, P_Y_INV, [&] { return launch_y<T>(W, g, 6, p->ay, twy, true, p->tune, s); }), "y_inv launch");
+  EQ_HIP(timed(p, P_Z_C2R, [&] {
+           return launch_z_c2r<T>(W, static_cast<T*>(s_eq), 6 * M, M, static_cast<const T*>(s_in),
+                                  static_cast<T*>(s_removed), 6, g, p->az, twz, p->tune, s);
+         }),
+         "z_c2r launch");
+  return EQ_OK;
+}
+
+template <typename T>
+eq_status run_check_finite(eq_plan_s* p, const void* s_in) {
+  const size_t n = (size_t)p->g.batch * 6 * field_elems(p);
+  EQ_HIP(launch_fill_int(p->flag, 1, 0, p->stream), "fill launch");
+  EQ_HIP(timed(p, P_CHECK, [&] { return launch_check_finite<T>(static_cast<const T*>(s_in), n, p->flag, p->stream); }),
+         "check_finite launch");
+  int h = 0;
+  EQ_HIP(hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream), "hipMemcpyAsync");
+  EQ_HIP(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  if (h) return fail(EQ_ERR_NONFINITE, "input holds a NaN or Inf");
+  return EQ_OK;
+}
+
+template <typename T>
+eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out) {
+  using C = cplx<T>;
+  const Geom& g = p->g;
+  hipStream_t st = p->stream;
+  const size_t M = field_elems(p);
+  if (p->desc.op == EQ_OP_DDO) {
+    EQ_HIP(timed(p, P_DIV_DDO, [&] {
+             return launch_div_ddo<T>(static_cast<const T*>(s), static_cast<T*>(div_out), p->partials, kRedBlocks, g,
+                                      p->desc.h, st);
+           }),
+           "div_ddo launch");
+  } else {
+    C* W = static_cast<C*>(p->W);
+    const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
+    const C* twx = tw;
+    const C* twy = tw + g.nx;
+    const C* twz = tw + g.nx + g.ny;
+    const size_t Q = spectrum_plane_elems(p);
+    // divergence field destination: the caller's buffer, else the upper half of each field's workspace
+    T* dst = static_cast<T*>(div_out);
+    size_t dfield = 3 * M, dcomp = M;
+    if (!dst) {
+      dst = reinterpret_cast<T*>(W + 3 * Q);
+      dfield = 2 * 6 * Q;
+    }
+    EQ_HIP(timed(p, P_Z_R2C, [&] { return launch_z_r2c<T>(static_cast<const T*>(s), W, g, p->az, twz, p->tune, st); }),
+           "z_r2c launch");
+    EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, 6, p->ay, twy, false, p->tune, st); }), "y_fwd launch");
+    EQ_HIP(timed(p, P_X_DIV, [&] { return launch_x<T>(W, g, XM_FWD | XM_DIV | XM_INV, p->ax, twx, p->sym, p->tune, st); }),
+           "x_div launch");
+    EQ_HIP(timed(p, P_Y_INV3, [&] { return launch_y<T>(W, g, 3, p->ay, twy, true, p->tune, st); }), "y_inv3 launch");
+    EQ_HIP(timed(p, P_Z_C2R3, [&] {
+             return launch_z_c2r<T>(W, dst, dfield, dcomp, nullptr, nullptr, 3, g, p->az, twz, p->tune, st);
+           }),
+           "z_c2r3 launch");
+    EQ_HIP(timed(p, P_DIV_STATS, [&] {
+             return launch_div_stats<T>(dst, dfield, dcomp, static_cast<const T*>(s), p->partials, kRedBlocks, g, st);
+           }),
+           "div_stats launch");
+  }
+  EQ_HIP(timed(p, P_REDUCE, [&] { return launch_reduce_final(p->partials, kRedBlocks, g.batch, p->red, st); }),
+         "reduce launch");
+  std::vector<double> host((size_t)g.batch * kRedWidth);
+  EQ_HIP(hipMemcpyAsync(host.data(), p->red, host.size() * sizeof(double), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  EQ_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  // max_q |s(q)| per axis, from the symbol definitions (Section 4.1 / 4.2)
+  double smax2 = 0.0;
+  const int dims[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    double m = 0.0;
+    for (int q = 0; q < dims[a]; ++q) {
+      double v;
+      const int n = dims[a];
+      if (p->desc.op == EQ_OP_CDO) {
+        const int k = (2 * q < n) ? q : ((2 * q == n) ? 0 : q - n);
+        v = 2.0 * M_PI * k / (n * p->desc.h);
+      } else {
+        v = ((2 * q) % n == 0) ? 0.0 : std::sin(2.0 * M_PI * q / n) / p->desc.h;
+      }
+      m = std::max(m, v * v);
+    }
+    smax2 += m;
+  }
+  const double w[6] = {1, 1, 1, 2, 2, 2};
+  for (int b = 0; b < g.batch; ++b) {
+    const double* r = &host[(size_t)b * kRedWidth];
+    double dev2 = 0.0;
+    for (int c = 0; c < 6; ++c) dev2 += w[c] * (r[8 + c] - r[2 + c] * r[2 + c] / (double)M);
+    const double l2 = std::sqrt(r[0]);
+    const double denom = std::sqrt(smax2) * std::sqrt(std::max(dev2, 0.0));
+    norms[3 * b + 0] = l2;
+    norms[3 * b + 1] = std::sqrt(r[1]);
+    norms[3 * b + 2] = denom > 0.0 ? l2 / denom : 0.0;
+  }
+  return EQ_OK;
+}
+
+bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() { if (prev >= 0) (void)hipSetDevice(prev); }
+};
+
+}  // namespace
+
+// =================================================================== ABI ====
+
+extern "C" {
+
+const char* eq_status_str(eq_status s) {
+  switch (s) {
+    case EQ_OK: return "EQ_OK";
+    case EQ_ERR_ARG: return "EQ_ERR_ARG";
+    case EQ_ERR_SIZE: return "EQ_ERR_SIZE";
+    case EQ_ERR_NOMEM: return "EQ_ERR_NOMEM";
+    case EQ_ERR_DEVICE: return "EQ_ERR_DEVICE";
+    case EQ_ERR_NONFINITE: return "EQ_ERR_NONFINITE";
+  }
+  return "EQ_ERR_UNKNOWN";
+}
+
+const char* eq_last_error(void) { return g_last_error.c_str(); }
+
+const char* eq_version(void) { return "libeq 0.1 gfx950"; }
+
+eq_status eq_plan_footprint(const eq_desc* d, size_t* bytes) {
+  if (!bytes) return fail(EQ_ERR_ARG, "null output pointer");
+  eq_status st = validate(d);
+  if (st != EQ_OK) return st;
+  *bytes = layout_of(d).total();
+  return EQ_OK;
+}
+
+eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out) {
+  if (!out) return fail(EQ_ERR_ARG, "null plan output pointer");
+  *out = nullptr;
+  eq_status st = validate(d);
+  if (st != EQ_OK) return st;
+  eq_plan_s* p = new (std::nothrow) eq_plan_s();
+  if (!p) return fail(EQ_ERR_NOMEM, "host allocation failed");
+  p->desc = *d;
+  factor_axis(d->nx, &p->ax);
+  factor_axis(d->ny, &p->ay);
+  factor_axis(d->nz, &p->az);
+  p->g = Geom{d->nx, d->ny, d->nz, d->nz / 2 + 1, d->batch};
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }
+  if ((st = check_lds(p)) != EQ_OK) { release(p); return st; }
+  if (d->flags & EQ_F_OWN_STREAM) {
+    e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { release(p); return hip_fail(e, "hipStreamCreateWithFlags"); }
+    p->own_stream = true;
+  } else {
+    p->stream = static_cast<hipStream_t>(hip_stream);
+  }
+  const Layout L = layout_of(d);
+  if ((st = dev_alloc(&p->W, L.w_bytes, "workspace")) != EQ_OK ||
+      (st = dev_alloc((void**)&p->sym, L.sym_bytes, "symbols")) != EQ_OK ||
+      (st = dev_alloc((void**)&p->tw64, L.tw64_bytes, "twiddles64")) != EQ_OK ||
+      (st = dev_alloc((void**)&p->tw32, L.tw32_bytes, "twiddles32")) != EQ_OK ||
+      (st = dev_alloc((void**)&p->partials, L.part_bytes, "partials")) != EQ_OK ||
+      (st = dev_alloc((void**)&p->red, L.red_bytes, "reduction")) != EQ_OK ||
+      (st = dev_alloc((void**)&p->flag, L.flag_bytes, "flag")) != EQ_OK) {
+    release(p);
+    return st;
+  }
+  e = launch_tables(p->g, d->op, d->h, p->sym, p->tw64, p->tw32, p->stream);
+  if (e != hipSuccess) { release(p); return hip_fail(e, "table kernel launch"); }
+  *out = p;
+  return EQ_OK;
+}
+
+eq_status eq_plan_destroy(eq_plan_t p) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  DeviceGuard dg(p->device);
+  (void)hipStreamSynchronize(p->stream);
+  release(p);
+  return EQ_OK;
+}
+
+eq_status eq_plan_set_stream(eq_plan_t p, void* hip_stream) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  DeviceGuard dg(p->device);
+  drop_graphs(p);
+  if (p->own_stream) {
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipStreamDestroy(p->stream);
+    p->own_stream = false;
+  }
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  return EQ_OK;
+}
+
+eq_status eq_project(eq_plan_t p, const void* s_in, void* s_eq, void* s_removed) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  if (!s_in || !s_eq) return fail(EQ_ERR_ARG, "null input or output pointer");
+  const size_t bytes = (size_t)p->g.batch * 6 * field_elems(p) * elem_size(&p->desc);
+  if (s_removed && (ranges_overlap(s_removed, s_in, bytes) || ranges_overlap(s_removed, s_eq, bytes)))
+    return fail(EQ_ERR_ARG, "s_removed overlaps s_in or s_eq");
+  if (s_eq != s_in && ranges_overlap(s_eq, s_in, bytes))
+    return fail(EQ_ERR_ARG, "s_eq partially overlaps s_in");
+  DeviceGuard dg(p->device);
+  const bool fp64 = p->desc.prec == EQ_FP64;
+  if (p->desc.flags & EQ_F_CHECK_FINITE) {
+    eq_status st = fp64 ? run_check_finite<double>(p, s_in) : run_check_finite<float>(p, s_in);
+    if (st != EQ_OK) return st;
+  }
+  if ((p->desc.flags & EQ_F_CAPTURE_GRAPH) && p->stream == nullptr)
+    return fail(EQ_ERR_ARG, "EQ_F_CAPTURE_GRAPH needs a stream other than the null stream");
+  const bool use_graph = (p->desc.flags & EQ_F_CAPTURE_GRAPH) && !p->timing;
+  if (!use_graph) return fp64 ? run_project<double>(p, s_in, s_eq, s_removed) : run_project<float>(p, s_in, s_eq, s_removed);
+  for (auto& ge : p->graphs)
+    if (ge.in == s_in && ge.eq == s_eq && ge.rem == s_removed) {
+      EQ_HIP(hipGraphLaunch(ge.exec, p->stream), "hipGraphLaunch");
+      return EQ_OK;
+    }
+  eq_plan_s::GraphEntry ge{s_in, s_eq, s_removed, nullptr, nullptr};
+  EQ_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  eq_status st = fp64 ? run_project<double>(p, s_in, s_eq, s_removed) : run_project<float>(p, s_in, s_eq, s_removed);
+  hipError_t e = hipStreamEndCapture(p->stream, &ge.graph);
+  if (st != EQ_OK) { if (ge.graph) (void)hipGraphDestroy(ge.graph); return st; }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) { (void)hipGraphDestroy(ge.graph); return hip_fail(e, "hipGraphInstantiate"); }
+  if (p->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(p->graphs.front().exec);
+    (void)hipGraphDestroy(p->graphs.front().graph);
+    p->graphs.erase(p->graphs.begin());
+  }
+  p->graphs.push_back(ge);
+  EQ_HIP(hipGraphLaunch(ge.exec, p->stream), "hipGraphLaunch");
+  return EQ_OK;
+}
+
+eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_out) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  if (!s || !norms_host) return fail(EQ_ERR_ARG, "null field or norms pointer");
+  const size_t es = elem_size(&p->desc);
+  if (div_out && ranges_overlap(div_out, s, (size_t)p->g.batch * 6 * field_elems(p) * es))
+    return fail(EQ_ERR_ARG, "div_out overlaps the field");
+  DeviceGuard dg(p->device);
+  return p->desc.prec == EQ_FP64 ? run_residual<double>(p, s, norms_host, div_out)
+                                 : run_residual<float>(p, s, norms_host, div_out);
+}
+
+eq_status eq_plan_set_timing(eq_plan_t p, int enable) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  p->timing = enable != 0;
+  return EQ_OK;
+}
+
+eq_status eq_plan_reset_stats(eq_plan_t p) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  DeviceGuard dg(p->device);
+  EQ_HIP(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  for (auto& r : p->pending) { p->event_pool.push_back(r.a); p->event_pool.push_back(r.b); }
+  p->pending.clear();
+  for (int i = 0; i < P_COUNT; ++i) { p->launches[i] = 0; p->total_ms[i] = 0.0; }
+  return EQ_OK;
+}
+
+eq_status eq_plan_pass_stats(eq_plan_t p, int max, int* count, const char** names, long long* launches,
+                             double* total_ms, double* bytes_per_launch) {
+  if (!p || !count) return fail(EQ_ERR_ARG, "null plan or count");
+  DeviceGuard dg(p->device);
+  if (!p->pending.empty()) {
+    EQ_HIP(hipEventSynchronize(p->pending.back().b), "hipEventSynchronize");
+    for (auto& r : p->pending) {
+      float ms = 0.f;
+      EQ_HIP(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+      p->total_ms[r.pass] += ms;
+      p->launches[r.pass] += 1;
+      p->event_pool.push_back(r.a);
+      p->event_pool.push_back(r.b);
+    }
+    p->pending.clear();
+  }
+  *count = P_COUNT;
+  for (int i = 0; i < P_COUNT && i < max; ++i) {
+    if (names) names[i] = kPassNames[i];
+    if (launches) launches[i] = p->launches[i];
+    if (total_ms) total_ms[i] = p->total_ms[i];
+    if (bytes_per_launch) bytes_per_launch[i] = pass_bytes(p, i);
+  }
+  return EQ_OK;
+}
+
+eq_status eq_debug_forward(eq_plan_t p, const void* s_in, void* spec_out) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  if (!s_in || !spec_out) return fail(EQ_ERR_ARG, "null pointer");
+  DeviceGuard dg(p->device);
+  auto go = [&](auto tag) -> eq_status {
+    using T = decltype(tag);
+    using C = cplx<T>;
+    C* W = static_cast<C*>(spec_out);
+    const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
+    EQ_HIP(launch_z_r2c<T>(static_cast<const T*>(s_in), W, p->g, p->az, tw + p->g.nx + p->g.ny, p->tune, p->stream), "z_r2c");
+    EQ_HIP(launch_y<T>(W, p->g, 6, p->ay, tw + p->g.nx, false, p->tune, p->stream), "y_fwd");
+    EQ_HIP(launch_x<T>(W, p->g, XM_FWD, p->ax, tw, p->sym, p->tune, p->stream), "x_fwd");
+    return EQ_OK;
+  };
+  return p->desc.prec == EQ_FP64 ? go(double{}) : go(float{});
+}
+
+eq_status eq_debug_project_spectrum(eq_plan_t p, void* spec) {
+  if (!p || !spec) return fail(EQ_ERR_ARG, "null pointer");
+  DeviceGuard dg(p->device);
+  auto go = [&](auto tag) -> eq_status {
+    using T = decltype(tag);
+    using C = cplx<T>;
+    const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
+    EQ_HIP(launch_x<T>(static_cast<C*>(spec), p->g, XM_PROJ, p->ax, tw, p->sym, p->tune, p->stream), "proj_only");
+    return EQ_OK;
+  };
+  return p->desc.prec == EQ_FP64 ? go(double{}) : go(float{});
+}
+
+}  // extern "C"

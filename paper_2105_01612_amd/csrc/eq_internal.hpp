@@ -1,0 +1,87 @@
+// eq_internal.hpp -- host-side interface between the plan (eq_capi.cpp) and the
+// kernel launchers (eq_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+#include "eq_fft.hpp"
+
+namespace eq {
+
+// Grid geometry of one plan.  The spectrum workspace W holds, per field, the
+// Hermitian half along z: (batch, 6, nzh = nz/2 + 1, ny, nx) complex.
+struct Geom {
+  int nx, ny, nz, nzh, batch;
+};
+
+struct AxisFft {
+  FftDesc d;   // radix schedule of this axis
+  int E;       // nominal elements per thread (2, 4 or 8)
+};
+
+// Launch shape knobs (0 = library default).  The autotuner may set them.
+struct Tune {
+  int tx_y = 0;    // x-tile width of the y pass (lines per workgroup)
+  int tx_z = 0;    // x-tile width of the z passes (real columns per workgroup, even)
+  int rw_x = 0;    // rows per workgroup of the fused x pass
+};
+
+// Modes of the fused x pass.
+enum XMode : int {
+  XM_FWD = 1,        // forward DFT along x
+  XM_PROJ = 2,       // per-frequency projection P A P
+  XM_INV = 4,        // inverse DFT along x
+  XM_DIV = 8,        // per-frequency divergence i s_j A_ij -> components 0..2
+};
+
+// Symbol table layout: sym[0 .. nx) x-axis, sym[nx .. nx+ny) y, sym[nx+ny .. +nz) z.
+// Twiddle tables: tw[off_a + m] = exp(-2 pi i m / n_a) with off_x = 0, off_y = nx, off_z = nx + ny.
+
+hipError_t launch_tables(const Geom& g, int op, double h, double* sym, double2* tw64, float2* tw32,
+                         hipStream_t s);
+
+template <typename T>
+hipError_t launch_z_r2c(const T* in, cplx<T>* W, const Geom& g, const AxisFft& az, const cplx<T>* tw_z,
+                        const Tune& tn, hipStream_t s);
+
+template <typename T>
+hipError_t launch_y(cplx<T>* W, const Geom& g, int ncomp, const AxisFft& ay, const cplx<T>* tw_y, bool inv,
+                    const Tune& tn, hipStream_t s);
+
+template <typename T>
+hipError_t launch_x(cplx<T>* W, const Geom& g, int mode, const AxisFft& ax, const cplx<T>* tw_x,
+                    const double* sym, const Tune& tn, hipStream_t s);
+
+// out(b, c, z, y, x) = out + b * out_field + c * out_comp + (z * ny + y) * nx + x for c < ncomp.
+// removed (nullable) = in - out at the same offsets.
+template <typename T>
+hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_comp, const T* in, T* removed,
+                        int ncomp, const Geom& g, const AxisFft& az, const cplx<T>* tw_z, const Tune& tn,
+                        hipStream_t s);
+
+// Reduction record per field (kRedWidth doubles):
+//   [0] sum_x |r|^2, [1] max_x |r|^2, [2..7] sum_x S_c, [8..13] sum_x S_c^2
+constexpr int kRedWidth = 14;
+
+template <typename T>
+hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk, const Geom& g, double h,
+                          hipStream_t s);
+
+template <typename T>
+hipError_t launch_div_stats(const T* div, size_t div_field, size_t div_comp, const T* S, double* partials,
+                            int nblk, const Geom& g, hipStream_t s);
+
+hipError_t launch_reduce_final(const double* partials, int nblk, int batch, double* out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_check_finite(const T* in, size_t n, int* flag, hipStream_t s);
+
+hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s);
+
+// Launch shapes the launchers pick (exposed so the plan can size LDS and report).
+int pick_tx_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);
+int pick_tx_z(const Geom& g, const AxisFft& az, int elem_bytes, const Tune& tn);
+int pick_rw_x(const Geom& g, const AxisFft& ax, int elem_bytes, const Tune& tn);
+
+}  // namespace eq

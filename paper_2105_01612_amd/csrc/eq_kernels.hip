@@ -1,0 +1,611 @@
+// eq_kernels.hip -- gfx950 kernels of the equilibrium projection and their launchers.
+//
+// Pass schedule of one projection (Section 3.3 solution strategy, evaluated in
+// Fourier space as in Section 4):
+//   z_r2c  real field -> Hermitian half spectrum along z (two real x-columns are
+//          packed into one complex line and separated after the transform)
+//   y fwd  complex DFT along y
+//   x proj complex DFT along x, per-frequency projection P A P over all six
+//          components of the frequency, inverse DFT along x (one read, one write)
+//   y inv  inverse DFT along y
+//   z_c2r  Hermitian half -> real along z, 1/(nx ny nz), optional removed part
+// Every pass reads its tile into LDS once, transforms it there and writes it
+// once; strided passes tile over contiguous x so every global access is a
+// contiguous run of tile-width elements.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "eq_fft.hpp"
+#include "eq_internal.hpp"
+
+namespace eq {
+
+namespace {
+
+constexpr int kMaxThreads = 1024;
+constexpr size_t kLdsPreferred = 64 * 1024;
+
+inline int elem_E(int n) { return (n % 8 == 0) ? 8 : ((n % 4 == 0) ? 4 : 2); }
+
+// ------------------------------------------------------------- tables ------
+
+__global__ void k_tables(int nx, int ny, int nz, int op, double h, double* __restrict__ sym,
+                         double2* __restrict__ tw64, float2* __restrict__ tw32) {
+  const int total = nx + ny + nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    int n, q;
+    if (i < nx) { n = nx; q = i; }
+    else if (i < nx + ny) { n = ny; q = i - nx; }
+    else { n = nz; q = i - nx - ny; }
+    // twiddle exp(-2 pi i q / n), FP64 on the device (sincospi is exact at multiples of 1/2)
+    double sn, cs;
+    sincospi(2.0 * (double)q / (double)n, &sn, &cs);
+    tw64[i] = make_double2(cs, -sn);
+    tw32[i] = make_float2((float)cs, (float)(-sn));
+    // derivative symbol of the operator (Section 4.1 eq:cdo, Section 4.2 eq:diff)
+    double s;
+    if (op == 0) {
+      const int k = (2 * q < n) ? q : ((2 * q == n) ? 0 : q - n);
+      s = 2.0 * M_PI * (double)k / ((double)n * h);
+    } else {
+      s = ((2 * q) % n == 0) ? 0.0 : sinpi(2.0 * (double)q / (double)n) / h;
+    }
+    sym[i] = s;
+  }
+}
+
+// ------------------------------------------------------------- z r2c -------
+
+struct ZArgs {
+  int nx, ny, nz, tx;      // tx: real x-columns per workgroup (even)
+};
+
+template <typename T, int E>
+__global__ __launch_bounds__(kMaxThreads) void k_z_r2c(const T* __restrict__ in, cplx<T>* __restrict__ W, ZArgs a,
+                                                       FftDesc d, const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int y = bid % a.ny;
+  const int bc = bid / a.ny;                        // b * 6 + c
+  const int np = a.tx >> 1;                         // complex lines (column pairs)
+  const int nz = a.nz, nzh = nz / 2 + 1;
+  const size_t plane = (size_t)a.ny * a.nx;
+  const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  for (int u = threadIdx.x; u < nz * np; u += blockDim.x) {
+    const int z = u / np, j = u - z * np;
+    lds[u] = *reinterpret_cast<const C*>(src + (size_t)z * plane + 2 * j);
+  }
+  __syncthreads();
+  fft_lines<T, E, false>(lds, np, 1, np, d, tw, threadIdx.x);
+  C* dst = W + (size_t)bc * nzh * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  const T half = (T)0.5;
+  for (int u = threadIdx.x; u < nzh * np; u += blockDim.x) {
+    const int kz = u / np, j = u - kz * np;
+    const C Z = lds[kz * np + j];
+    const C Zm = lds[((nz - kz) % nz) * np + j];
+    // A = (Z + conj Zm) / 2 and B = (Z - conj Zm) / 2i are the spectra of the two columns
+    C A = mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
+    C B = mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half);
+    C* o = dst + (size_t)kz * plane + 2 * j;
+    o[0] = A;
+    o[1] = B;
+  }
+}
+
+// ------------------------------------------------------------- y pass ------
+
+struct YArgs {
+  int nx, ny, nzh, ncomp, tx;
+};
+
+template <typename T, int E, bool INV>
+__global__ __launch_bounds__(kMaxThreads) void k_y(cplx<T>* __restrict__ W, YArgs a, FftDesc d,
+                                                   const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int kz = bid % a.nzh; bid /= a.nzh;
+  const int c = bid % a.ncomp;
+  const int b = bid / a.ncomp;
+  C* base = W + (((size_t)(b * 6 + c) * a.nzh + kz) * a.ny) * a.nx + (size_t)xt * a.tx;
+  const int tx = a.tx;
+  for (int u = threadIdx.x; u < a.ny * tx; u += blockDim.x) {
+    const int y = u / tx, x = u - y * tx;
+    lds[u] = base[(size_t)y * a.nx + x];
+  }
+  __syncthreads();
+  fft_lines<T, E, INV>(lds, tx, 1, tx, d, tw, threadIdx.x);
+  for (int u = threadIdx.x; u < a.ny * tx; u += blockDim.x) {
+    const int y = u / tx, x = u - y * tx;
+    base[(size_t)y * a.nx + x] = lds[u];
+  }
+}
+
+// ------------------------------------------------------------- x pass ------
+
+struct XArgs {
+  int nx, ny, nzh, rows, rw, mode;   // rows = batch * nzh * ny
+};
+
+// Projection of one frequency: out = P A P, P = I - n n^T, n = s / |s| formed in FP64.
+// Voigt slots: 0=11 1=22 2=33 3=23 4=13 5=12.
+template <typename T>
+__device__ __forceinline__ void project_one(cplx<T>* A /*6*/, double sx, double sy, double sz) {
+  using C = cplx<T>;
+  const double ss = sx * sx + sy * sy + sz * sz;
+  if (!(ss > 0.0)) return;                                   // zero symbol: divergence-free, kept
+  const double inv = 1.0 / sqrt(ss);
+  const T n0 = (T)(sx * inv), n1 = (T)(sy * inv), n2 = (T)(sz * inv);
+  const C a00 = A[0], a11 = A[1], a22 = A[2], a12 = A[3], a02 = A[4], a01 = A[5];
+  // b = A n
+  C b0, b1, b2;
+  b0.x = a00.x * n0 + a01.x * n1 + a02.x * n2;  b0.y = a00.y * n0 + a01.y * n1 + a02.y * n2;
+  b1.x = a01.x * n0 + a11.x * n1 + a12.x * n2;  b1.y = a01.y * n0 + a11.y * n1 + a12.y * n2;
+  b2.x = a02.x * n0 + a12.x * n1 + a22.x * n2;  b2.y = a02.y * n0 + a12.y * n1 + a22.y * n2;
+  // c = n . b
+  C cc;
+  cc.x = n0 * b0.x + n1 * b1.x + n2 * b2.x;
+  cc.y = n0 * b0.y + n1 * b1.y + n2 * b2.y;
+  // out_ij = A_ij - n_i b_j - b_i n_j + c n_i n_j
+  auto upd = [&](C aij, T ni, T nj, C bi, C bj) -> C {
+    C o;
+    const T nn = ni * nj;
+    o.x = aij.x - ni * bj.x - nj * bi.x + cc.x * nn;
+    o.y = aij.y - ni * bj.y - nj * bi.y + cc.y * nn;
+    return o;
+  };
+  A[0] = upd(a00, n0, n0, b0, b0);
+  A[1] = upd(a11, n1, n1, b1, b1);
+  A[2] = upd(a22, n2, n2, b2, b2);
+  A[3] = upd(a12, n1, n2, b1, b2);
+  A[4] = upd(a02, n0, n2, b0, b2);
+  A[5] = upd(a01, n0, n1, b0, b1);
+}
+
+template <typename T, int E>
+__global__ __launch_bounds__(kMaxThreads) void k_x(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
+                                                   const cplx<T>* __restrict__ tw, const double* __restrict__ sym) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int nx = a.nx, ls = nx + 1, rw = a.rw;
+  const int row0 = blockIdx.x * rw;
+  const int nrows = min(rw, a.rows - row0);
+  const size_t plane = (size_t)a.ny * nx;
+  const int per_field = a.nzh * a.ny;
+  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  auto row_base = [&](int row, int c) -> size_t {
+    const int b = row / per_field;
+    const int rem = row - b * per_field;       // kz * ny + ky
+    return ((size_t)(b * 6 + c) * a.nzh) * plane + (size_t)rem * nx;
+  };
+  // load 6 components x rw rows, contiguous along x
+  for (int c = 0; c < 6; ++c) {
+    for (int u = threadIdx.x; u < rw * nx; u += blockDim.x) {
+      const int r = u / nx, x = u - r * nx;
+      C v = mk<T>((T)0, (T)0);
+      if (r < nrows) v = W[row_base(row0 + r, c) + x];
+      lds[(c * rw + r) * ls + x] = v;
+    }
+  }
+  __syncthreads();
+  if (a.mode & XM_FWD) fft_lines<T, E, false>(lds, 6 * rw, ls, 1, d, tw, threadIdx.x);
+  if (a.mode & (XM_PROJ | XM_DIV)) {
+    const double* symx = sym;
+    const double* symy = sym + nx;
+    const double* symz = sym + nx + a.ny;
+    for (int u = threadIdx.x; u < nrows * nx; u += blockDim.x) {
+      const int r = u / nx, kx = u - r * nx;
+      const int row = row0 + r;
+      const int rem = row % per_field;
+      const int kz = rem / a.ny, ky = rem - kz * a.ny;
+      C A[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) A[c] = lds[(c * rw + r) * ls + kx];
+      if (a.mode & XM_PROJ) {
+        project_one<T>(A, symx[kx], symy[ky], symz[kz]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) lds[(c * rw + r) * ls + kx] = A[c];
+      } else {
+        // divergence r_i = sum_j (i s_j) A_ij
+        const T s0 = (T)symx[kx], s1 = (T)symy[ky], s2 = (T)symz[kz];
+        C r3[3];
+        const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const C p = A[idx[i][0]], q = A[idx[i][1]], w = A[idx[i][2]];
+          const T re = s0 * p.x + s1 * q.x + s2 * w.x;
+          const T im = s0 * p.y + s1 * q.y + s2 * w.y;
+          r3[i] = mk<T>(-im, re);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lds[(i * rw + r) * ls + kx] = r3[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (a.mode & XM_INV) fft_lines<T, E, true>(lds, ncomp_out * rw, ls, 1, d, tw, threadIdx.x);
+  for (int c = 0; c < ncomp_out; ++c) {
+    for (int u = threadIdx.x; u < nrows * nx; u += blockDim.x) {
+      const int r = u / nx, x = u - r * nx;
+      W[row_base(row0 + r, c) + x] = lds[(c * rw + r) * ls + x];
+    }
+  }
+}
+
+// ------------------------------------------------------------- z c2r -------
+
+struct ZcArgs {
+  int nx, ny, nz, tx, ncomp;
+  size_t out_field, out_comp;
+};
+
+template <typename T, int E>
+__global__ __launch_bounds__(kMaxThreads) void k_z_c2r(const cplx<T>* __restrict__ W, T* out, const T* in, T* removed,
+                                                       ZcArgs a, FftDesc d, const cplx<T>* __restrict__ tw, T scale) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int y = bid % a.ny; bid /= a.ny;
+  const int c = bid % a.ncomp;
+  const int b = bid / a.ncomp;
+  const int np = a.tx >> 1;
+  const int nz = a.nz, nzh = nz / 2 + 1, nyq = nz / 2;
+  const size_t plane = (size_t)a.ny * a.nx;
+  const C* src = W + ((size_t)(b * 6 + c) * nzh) * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  for (int u = threadIdx.x; u < nzh * np; u += blockDim.x) {
+    const int kz = u / np, j = u - kz * np;
+    const C* s = src + (size_t)kz * plane + 2 * j;
+    C A = s[0], B = s[1];
+    if (kz == 0 || kz == nyq) { A.y = (T)0; B.y = (T)0; }   // self-conjugate planes are real
+    lds[kz * np + j] = mk<T>(A.x - B.y, A.y + B.x);                    // A + i B
+    if (kz > 0 && kz < nyq) lds[(nz - kz) * np + j] = mk<T>(A.x + B.y, B.x - A.y);  // conj A + i conj B
+  }
+  __syncthreads();
+  fft_lines<T, E, true>(lds, np, 1, np, d, tw, threadIdx.x);
+  const size_t obase = (size_t)b * a.out_field + (size_t)c * a.out_comp + (size_t)y * a.nx + (size_t)xt * a.tx;
+  for (int u = threadIdx.x; u < nz * np; u += blockDim.x) {
+    const int z = u / np, j = u - z * np;
+    const C Z = lds[u];
+    const size_t off = obase + (size_t)z * plane + 2 * j;
+    C o = mk<T>(Z.x * scale, Z.y * scale);
+    if (removed) {
+      const C s = *reinterpret_cast<const C*>(in + off);
+      *reinterpret_cast<C*>(removed + off) = mk<T>(s.x - o.x, s.y - o.y);
+    }
+    *reinterpret_cast<C*>(out + off) = o;
+  }
+}
+
+// ------------------------------------------------------------ residual -----
+
+constexpr int kRedThreads = 256;
+
+// Deterministic block reduction of the kRedWidth record (sums, except [1] = max).
+__device__ __forceinline__ void block_reduce_record(double* v, double* sh /* kRedWidth * kRedThreads */) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kRedWidth; ++k) sh[k * kRedThreads + t] = v[k];
+  __syncthreads();
+  for (int stride = kRedThreads / 2; stride > 0; stride >>= 1) {
+    if (t < stride) {
+#pragma unroll
+      for (int k = 0; k < kRedWidth; ++k) {
+        const double o = sh[k * kRedThreads + t + stride];
+        double& m = sh[k * kRedThreads + t];
+        m = (k == 1) ? fmax(m, o) : m + o;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kRedWidth; ++k) v[k] = sh[k * kRedThreads];
+}
+
+struct DArgs {
+  int nx, ny, nz;
+  double inv2h;
+};
+
+// DDO divergence in real space: periodic central differences, exactly the DDO symbol.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S, T* __restrict__ div,
+                                                         double* __restrict__ partials, DArgs a) {
+  __shared__ double sh[kRedWidth * kRedThreads];
+  const int b = blockIdx.y;
+  const size_t M = (size_t)a.nx * a.ny * a.nz;
+  const T* F = S + (size_t)b * 6 * M;
+  double acc[kRedWidth];
+#pragma unroll
+  for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+  const size_t sx = 1, sy = (size_t)a.nx, sz = (size_t)a.nx * a.ny;
+  for (size_t v = (size_t)blockIdx.x * kRedThreads + threadIdx.x; v < M; v += (size_t)gridDim.x * kRedThreads) {
+    const int x = (int)(v % a.nx);
+    const size_t t = v / a.nx;
+    const int y = (int)(t % a.ny);
+    const int z = (int)(t / a.ny);
+    const size_t xp = (x + 1 == a.nx) ? v + 1 - (size_t)a.nx * sx : v + sx;
+    const size_t xm = (x == 0) ? v + (size_t)(a.nx - 1) * sx : v - sx;
+    const size_t yp = (y + 1 == a.ny) ? v + sy - (size_t)a.ny * sy : v + sy;
+    const size_t ym = (y == 0) ? v + (size_t)(a.ny - 1) * sy : v - sy;
+    const size_t zp = (z + 1 == a.nz) ? v + sz - (size_t)a.nz * sz : v + sz;
+    const size_t zm = (z == 0) ? v + (size_t)(a.nz - 1) * sz : v - sz;
+    auto D = [&](int c, size_t p, size_t m) -> double {
+      return ((double)F[c * M + p] - (double)F[c * M + m]) * a.inv2h;
+    };
+    // r_x = d_x S11 + d_y S12 + d_z S13, etc. (slots 0=11 1=22 2=33 3=23 4=13 5=12)
+    const double r0 = D(0, xp, xm) + D(5, yp, ym) + D(4, zp, zm);
+    const double r1 = D(5, xp, xm) + D(1, yp, ym) + D(3, zp, zm);
+    const double r2 = D(4, xp, xm) + D(3, yp, ym) + D(2, zp, zm);
+    const double m2 = r0 * r0 + r1 * r1 + r2 * r2;
+    acc[0] += m2;
+    acc[1] = fmax(acc[1], m2);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double s = (double)F[c * M + v];
+      acc[2 + c] += s;
+      acc[8 + c] += s * s;
+    }
+    if (div) {
+      T* o = div + (size_t)b * 3 * M + v;
+      o[0] = (T)r0; o[M] = (T)r1; o[2 * M] = (T)r2;
+    }
+  }
+  block_reduce_record(acc, sh);
+  if (threadIdx.x == 0) {
+    double* p = partials + ((size_t)b * gridDim.x + blockIdx.x) * kRedWidth;
+#pragma unroll
+    for (int k = 0; k < kRedWidth; ++k) p[k] = acc[k];
+  }
+}
+
+struct DsArgs {
+  int nx, ny, nz;
+  size_t div_field, div_comp;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_div_stats(const T* __restrict__ div, const T* __restrict__ S,
+                                                           double* __restrict__ partials, DsArgs a) {
+  __shared__ double sh[kRedWidth * kRedThreads];
+  const int b = blockIdx.y;
+  const size_t M = (size_t)a.nx * a.ny * a.nz;
+  const T* F = S + (size_t)b * 6 * M;
+  const T* R = div + (size_t)b * a.div_field;
+  double acc[kRedWidth];
+#pragma unroll
+  for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+  for (size_t v = (size_t)blockIdx.x * kRedThreads + threadIdx.x; v < M; v += (size_t)gridDim.x * kRedThreads) {
+    const double r0 = R[v], r1 = R[a.div_comp + v], r2 = R[2 * a.div_comp + v];
+    const double m2 = r0 * r0 + r1 * r1 + r2 * r2;
+    acc[0] += m2;
+    acc[1] = fmax(acc[1], m2);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double s = (double)F[c * M + v];
+      acc[2 + c] += s;
+      acc[8 + c] += s * s;
+    }
+  }
+  block_reduce_record(acc, sh);
+  if (threadIdx.x == 0) {
+    double* p = partials + ((size_t)b * gridDim.x + blockIdx.x) * kRedWidth;
+#pragma unroll
+    for (int k = 0; k < kRedWidth; ++k) p[k] = acc[k];
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ partials, int nblk,
+                                                              double* __restrict__ out) {
+  __shared__ double sh[kRedWidth * kRedThreads];
+  const int b = blockIdx.x;
+  double acc[kRedWidth];
+#pragma unroll
+  for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kRedThreads) {
+    const double* p = partials + ((size_t)b * nblk + i) * kRedWidth;
+#pragma unroll
+    for (int k = 0; k < kRedWidth; ++k) acc[k] = (k == 1) ? fmax(acc[k], p[k]) : acc[k] + p[k];
+  }
+  block_reduce_record(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kRedWidth; ++k) out[(size_t)b * kRedWidth + k] = acc[k];
+  }
+}
+
+template <typename T>
+__global__ void k_check_finite(const T* __restrict__ p, size_t n, int* flag) {
+  int bad = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(p[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void k_fill_int(int* p, int n, int value) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = value;
+}
+
+template <typename T>
+size_t csize() { return sizeof(cplx<T>); }
+
+int round_threads(int t) { return t < 64 ? 64 : ((t + 63) / 64) * 64; }
+
+}  // namespace
+
+// ------------------------------------------------------------- shapes ------
+
+int pick_tx_y(const Geom& g, const AxisFft& ay, int eb, const Tune& tn) {
+  if (tn.tx_y > 0) return tn.tx_y;
+  const int P = g.ny / ay.E;
+  int tx = 64;
+  while (tx > 1 && (g.nx % tx != 0 || tx * P > kMaxThreads || (size_t)tx * g.ny * eb > kLdsPreferred)) tx >>= 1;
+  return tx;
+}
+
+int pick_tx_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
+  if (tn.tx_z > 0) return tn.tx_z;
+  const int P = g.nz / az.E;
+  int tx = 128;
+  while (tx > 2 && (g.nx % tx != 0 || (tx / 2) * P > kMaxThreads || (size_t)(tx / 2) * g.nz * eb > kLdsPreferred))
+    tx >>= 1;
+  return tx;
+}
+
+int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
+  if (tn.rw_x > 0) return tn.rw_x;
+  const int P = g.nx / ax.E;
+  int rw = 16;
+  while (rw > 1 && (6 * rw * P > kMaxThreads || (size_t)6 * rw * (g.nx + 1) * eb > kLdsPreferred)) --rw;
+  return rw;
+}
+
+// ----------------------------------------------------------- launchers -----
+
+hipError_t launch_tables(const Geom& g, int op, double h, double* sym, double2* tw64, float2* tw32, hipStream_t s) {
+  const int total = g.nx + g.ny + g.nz;
+  hipLaunchKernelGGL(k_tables, dim3((total + 255) / 256), dim3(256), 0, s, g.nx, g.ny, g.nz, op, h, sym, tw64, tw32);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_z_r2c(const T* in, cplx<T>* W, const Geom& g, const AxisFft& az, const cplx<T>* tw_z,
+                        const Tune& tn, hipStream_t s) {
+  const int eb = (int)csize<T>();
+  const int tx = pick_tx_z(g, az, eb, tn);
+  ZArgs a{g.nx, g.ny, g.nz, tx};
+  const int threads = round_threads((tx / 2) * (g.nz / az.E));
+  const size_t lds = (size_t)(tx / 2) * g.nz * eb;
+  const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.ny * g.batch * 6));
+  switch (az.E) {
+    case 8: hipLaunchKernelGGL((k_z_r2c<T, 8>), grid, dim3(threads), lds, s, in, W, a, az.d, tw_z); break;
+    case 4: hipLaunchKernelGGL((k_z_r2c<T, 4>), grid, dim3(threads), lds, s, in, W, a, az.d, tw_z); break;
+    default: hipLaunchKernelGGL((k_z_r2c<T, 2>), grid, dim3(threads), lds, s, in, W, a, az.d, tw_z); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_y(cplx<T>* W, const Geom& g, int ncomp, const AxisFft& ay, const cplx<T>* tw_y, bool inv,
+                    const Tune& tn, hipStream_t s) {
+  const int eb = (int)csize<T>();
+  const int tx = pick_tx_y(g, ay, eb, tn);
+  YArgs a{g.nx, g.ny, g.nzh, ncomp, tx};
+  const int threads = round_threads(tx * (g.ny / ay.E));
+  const size_t lds = (size_t)tx * g.ny * eb;
+  const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.nzh * ncomp * g.batch));
+#define EQ_LAUNCH_Y(EE)                                                                                    \
+  if (inv) hipLaunchKernelGGL((k_y<T, EE, true>), grid, dim3(threads), lds, s, W, a, ay.d, tw_y);         \
+  else hipLaunchKernelGGL((k_y<T, EE, false>), grid, dim3(threads), lds, s, W, a, ay.d, tw_y);
+  switch (ay.E) {
+    case 8: EQ_LAUNCH_Y(8) break;
+    case 4: EQ_LAUNCH_Y(4) break;
+    default: EQ_LAUNCH_Y(2) break;
+  }
+#undef EQ_LAUNCH_Y
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_x(cplx<T>* W, const Geom& g, int mode, const AxisFft& ax, const cplx<T>* tw_x, const double* sym,
+                    const Tune& tn, hipStream_t s) {
+  const int eb = (int)csize<T>();
+  const int rw = pick_rw_x(g, ax, eb, tn);
+  const int rows = g.batch * g.nzh * g.ny;
+  XArgs a{g.nx, g.ny, g.nzh, rows, rw, mode};
+  const int threads = round_threads(6 * rw * (g.nx / ax.E));
+  const size_t lds = (size_t)6 * rw * (g.nx + 1) * eb;
+  const dim3 grid((unsigned)((rows + rw - 1) / rw));
+  switch (ax.E) {
+    case 8: hipLaunchKernelGGL((k_x<T, 8>), grid, dim3(threads), lds, s, W, a, ax.d, tw_x, sym); break;
+    case 4: hipLaunchKernelGGL((k_x<T, 4>), grid, dim3(threads), lds, s, W, a, ax.d, tw_x, sym); break;
+    default: hipLaunchKernelGGL((k_x<T, 2>), grid, dim3(threads), lds, s, W, a, ax.d, tw_x, sym); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_comp, const T* in, T* removed,
+                        int ncomp, const Geom& g, const AxisFft& az, const cplx<T>* tw_z, const Tune& tn,
+                        hipStream_t s) {
+  const int eb = (int)csize<T>();
+  const int tx = pick_tx_z(g, az, eb, tn);
+  ZcArgs a{g.nx, g.ny, g.nz, tx, ncomp, out_field, out_comp};
+  const int threads = round_threads((tx / 2) * (g.nz / az.E));
+  const size_t lds = (size_t)(tx / 2) * g.nz * eb;
+  const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.ny * ncomp * g.batch));
+  const T scale = (T)(1.0 / ((double)g.nx * (double)g.ny * (double)g.nz));
+  switch (az.E) {
+    case 8: hipLaunchKernelGGL((k_z_c2r<T, 8>), grid, dim3(threads), lds, s, W, out, in, removed, a, az.d, tw_z, scale); break;
+    case 4: hipLaunchKernelGGL((k_z_c2r<T, 4>), grid, dim3(threads), lds, s, W, out, in, removed, a, az.d, tw_z, scale); break;
+    default: hipLaunchKernelGGL((k_z_c2r<T, 2>), grid, dim3(threads), lds, s, W, out, in, removed, a, az.d, tw_z, scale); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk, const Geom& g, double h, hipStream_t s) {
+  DArgs a{g.nx, g.ny, g.nz, 0.5 / h};
+  hipLaunchKernelGGL((k_div_ddo<T>), dim3(nblk, g.batch), dim3(kRedThreads), 0, s, S, div_out, partials, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_div_stats(const T* div, size_t div_field, size_t div_comp, const T* S, double* partials, int nblk,
+                            const Geom& g, hipStream_t s) {
+  DsArgs a{g.nx, g.ny, g.nz, div_field, div_comp};
+  hipLaunchKernelGGL((k_div_stats<T>), dim3(nblk, g.batch), dim3(kRedThreads), 0, s, div, S, partials, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(const double* partials, int nblk, int batch, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(batch), dim3(kRedThreads), 0, s, partials, nblk, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_check_finite(const T* in, size_t n, int* flag, hipStream_t s) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL((k_check_finite<T>), dim3((unsigned)blocks), dim3(256), 0, s, in, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, p, n, value);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ instantiations -----
+
+#define EQ_INSTANTIATE(T)                                                                                         \
+  template hipError_t launch_z_r2c<T>(const T*, cplx<T>*, const Geom&, const AxisFft&, const cplx<T>*,          \
+                                      const Tune&, hipStream_t);                                                  \
+  template hipError_t launch_y<T>(cplx<T>*, const Geom&, int, const AxisFft&, const cplx<T>*, bool, const Tune&, \
+                                  hipStream_t);                                                                   \
+  template hipError_t launch_x<T>(cplx<T>*, const Geom&, int, const AxisFft&, const cplx<T>*, const double*,     \
+                                  const Tune&, hipStream_t);                                                      \
+  template hipError_t launch_z_c2r<T>(const cplx<T>*, T*, size_t, size_t, const T*, T*, int, const Geom&,        \
+                                      const AxisFft&, const cplx<T>*, const Tune&, hipStream_t);                  \
+  template hipError_t launch_div_ddo<T>(const T*, T*, double*, int, const Geom&, double, hipStream_t);          \
+  template hipError_t launch_div_stats<T>(const T*, size_t, size_t, const T*, double*, int, const Geom&,        \
+                                          hipStream_t);                                                           \
+  template hipError_t launch_check_finite<T>(const T*, size_t, int*, hipStream_t);
+
+EQ_INSTANTIATE(float)
+EQ_INSTANTIATE(double)
+
+}  // namespace eq

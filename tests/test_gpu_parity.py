@@ -1,0 +1,346 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: rel-L2 (Frobenius, off-diagonals weigh 2) <= 1e-12 for FP64 and <= 1e-5 for
+FP32; FP32 runs are compared on the FP64 up-cast of the same FP32 input bytes.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2105_01612_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+W6 = np.array([1.0, 1.0, 1.0, 2.0, 2.0, 2.0])
+
+
+def torch_mod():
+    import torch
+
+    return torch
+
+
+def eqmod():
+    import paper_2105_01612_amd as eq
+
+    return eq
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def frob(x):
+    w = W6.reshape((6,) + (1,) * (x.ndim - 1)) if x.shape[0] == 6 else W6.reshape((1, 6) + (1,) * (x.ndim - 2))
+    return math.sqrt(float(np.sum(w * x.astype(np.float64) ** 2)))
+
+
+def rel_l2(got, ref):
+    return frob(got - ref) / frob(ref)
+
+
+def to_dev(a, prec):
+    torch = torch_mod()
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+
+
+def run_project(S, op, prec, h=1.0, removed=True, flags=0):
+    eq = eqmod()
+    torch = torch_mod()
+    batch = S.shape[0] if S.ndim == 5 else 1
+    nz, ny, nx = S.shape[-3:]
+    plan = eq.plan(nx, ny, nz, batch=batch, op=op, prec=prec, h=h, flags=flags)
+    x = to_dev(S, prec)
+    out = torch.empty_like(x)
+    rem = torch.empty_like(x) if removed else None
+    plan.project(x, out, rem)
+    torch.cuda.synchronize()
+    res = (out.double().cpu().numpy(), rem.double().cpu().numpy() if removed else None)
+    plan.destroy()
+    return res
+
+
+def upcast(S, prec):
+    return S.astype(np.float32).astype(np.float64) if prec == "fp32" else S
+
+
+# ----------------------------------------------------------------- stages ---
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 10, 16), (20, 12, 30), (32, 48, 40)])
+def test_forward_spectrum(prec, shape):
+    """eq_debug_forward: half spectrum along z of the unnormalized forward DFT."""
+    eq = eqmod()
+    torch = torch_mod()
+    say("forward", prec, shape)
+    S = wl.random_field(shape, seed=3, scale=10.0)
+    Su = upcast(S, prec)
+    nz, ny, nx = shape
+    plan = eq.plan(nx, ny, nz, op="ddo", prec=prec)
+    spec = torch.empty(plan.spectrum_shape, dtype=plan.dtype, device="cuda")
+    plan.debug_forward(to_dev(S, prec), spec)
+    torch.cuda.synchronize()
+    got = spec.double().cpu().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = np.fft.fftn(Su, axes=(1, 2, 3))[None, :, : nz // 2 + 1]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err <= (1e-14 if prec == "fp64" else 2e-6), err
+    plan.destroy()
+
+
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_projection_kernel_on_spectrum(op, prec):
+    """eq_debug_project_spectrum against the oracle's per-frequency P A P on identical spectra."""
+    eq = eqmod()
+    torch = torch_mod()
+    shape = (12, 10, 16)
+    nz, ny, nx = shape
+    h = 0.6
+    rng = np.random.default_rng(4)
+    spec = rng.standard_normal((1, 6, nz // 2 + 1, ny, nx, 2))
+    if prec == "fp32":
+        spec = spec.astype(np.float32).astype(np.float64)
+    plan = eq.plan(nx, ny, nz, op=op, prec=prec, h=h)
+    t = to_dev(spec, prec)
+    plan.debug_project_spectrum(t)
+    torch.cuda.synchronize()
+    got = t.double().cpu().numpy()
+    A = spec[0, ..., 0] + 1j * spec[0, ..., 1]
+    sx = O.axis_symbol(op, nx, h)
+    sy = O.axis_symbol(op, ny, h)
+    sz = O.axis_symbol(op, nz, h)[: nz // 2 + 1]
+    s = np.stack(np.broadcast_arrays(sx[None, None, :], sy[None, :, None], sz[:, None, None]))
+    ref = O.matrix_to_voigt(O.project_spectrum_pap(O.voigt_to_matrix(A), s))
+    g = got[0, ..., 0] + 1j * got[0, ..., 1]
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    assert err <= (1e-14 if prec == "fp64" else 1e-6), err
+    plan.destroy()
+
+
+# ------------------------------------------------------------ end to end ----
+
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+def test_config_small_fp64(op):
+    """32^3, 20 grains, FP64: S_eq and the removed part against the oracle."""
+    say("small fp64", op)
+    S = wl.config_field("small")
+    got, rem = run_project(S, op, "fp64")
+    ref, ref_rem = O.project(S, op)
+    assert rel_l2(got, ref) <= TOL["fp64"]
+    assert rel_l2(rem, ref_rem) <= 1e-11
+    assert np.max(np.abs(got + rem - S)) <= 1e-12 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (20, 12, 30), (36, 40, 48), (96, 96, 96), (6, 10, 4)])
+def test_project_parity(prec, op, shape):
+    say("project", prec, op, shape)
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=12, sigma_grain=100.0, sigma_noise=5.0, sigma_grad=1.0,
+                                      seed=sum(shape)))
+    got, rem = run_project(S, op, prec, h=0.5)
+    Su = upcast(S, prec)
+    ref, ref_rem = O.project(Su, op, 0.5)
+    assert rel_l2(got, ref) <= TOL[prec]
+    tol_rem = 1e-11 if prec == "fp64" else 3e-5
+    assert rel_l2(rem, ref_rem) <= tol_rem
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_equals_single_and_oracle(prec):
+    eq = eqmod()
+    torch = torch_mod()
+    n = 32
+    specs = wl.batched_specs(n=n, fields=3, grains=30, first_seed=300)
+    S = np.stack([wl.voronoi_field(sp) for sp in specs])
+    gotb, _ = run_project(S, "ddo", prec, removed=False)
+    for b in range(3):
+        single, _ = run_project(S[b], "ddo", prec, removed=False)
+        assert np.array_equal(single, gotb[b])
+        ref, _ = O.project(upcast(S[b], prec), "ddo")
+        assert rel_l2(gotb[b], ref) <= TOL[prec]
+
+
+def test_in_place_and_determinism():
+    eq = eqmod()
+    torch = torch_mod()
+    S = wl.config_field("small")
+    plan = eq.plan(32, op="ddo", prec="fp64")
+    x = to_dev(S, "fp64")
+    a = plan.project(x.clone())
+    b = plan.project(x.clone())
+    y = x.clone()
+    plan.project(y, y)                  # in place
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a, y)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_invariants_on_gpu_output(prec):
+    eq = eqmod()
+    torch = torch_mod()
+    n = 48
+    S = wl.voronoi_field(wl.FieldSpec((n, n, n), grains=40, sigma_grain=100.0, sigma_noise=5.0, seed=8))
+    for op in ("cdo", "ddo"):
+        plan = eq.plan(n, op=op, prec=prec)
+        x = to_dev(S, prec)
+        y = plan.project(x)
+        z = plan.project(y)
+        torch.cuda.synchronize()
+        Y = y.double().cpu().numpy()
+        Z = z.double().cpu().numpy()
+        Su = upcast(S, prec)
+        tol = 1e-12 if prec == "fp64" else 2e-6
+        # idempotent
+        assert rel_l2(Z, Y) <= tol
+        # mean kept
+        assert np.abs(Y.mean(axis=(1, 2, 3)) - Su.mean(axis=(1, 2, 3))).max() <= tol * np.abs(Su).max() * 10
+        # divergence-free in the same operator (oracle residual of the GPU output)
+        l2, mx, rel = O.residual_norms(Y, op)
+        assert rel <= (1e-14 if prec == "fp64" else 1e-6)
+        # orthogonality of removed part and the demeaned result
+        R = Su - Y
+        dev = Y - Y.mean(axis=(1, 2, 3), keepdims=True)
+        assert abs(O.frobenius_dot(R, dev)) <= (1e-12 if prec == "fp64" else 1e-5) * O.frobenius_norm(R) * O.frobenius_norm(dev)
+        plan.destroy()
+
+
+# -------------------------------------------------------------- residual ----
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+def test_residual_parity(op, prec):
+    eq = eqmod()
+    torch = torch_mod()
+    shape = (16, 24, 20)
+    nz, ny, nx = shape
+    h = 0.8
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=10, sigma_grain=50.0, sigma_noise=3.0, seed=5))
+    Su = upcast(S, prec)
+    plan = eq.plan(nx, ny, nz, op=op, prec=prec, h=h)
+    x = to_dev(S, prec)
+    div = torch.empty((1, 3, nz, ny, nx), dtype=plan.dtype, device="cuda")
+    norms = plan.residual(x, div)[0]
+    norms2 = plan.residual(x)[0]
+    ref = O.residual_norms(Su, op, h)
+    rdiv = O.divergence(Su, op, h)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for g, r in zip(norms, ref):
+        assert abs(g - r) <= tol * abs(r), (norms, ref)
+    assert norms == norms2
+    d = div.double().cpu().numpy()[0]
+    assert np.abs(d - rdiv).max() <= tol * np.abs(rdiv).max() * 10
+    plan.destroy()
+
+
+def test_residual_of_projection_is_roundoff():
+    eq = eqmod()
+    n = 64
+    S = wl.voronoi_field(wl.FieldSpec((n, n, n), grains=60, sigma_grain=100.0, sigma_noise=5.0, seed=9))
+    for prec, bound in (("fp64", 1e-14), ("fp32", 2e-6)):
+        for op in ("cdo", "ddo"):
+            plan = eq.plan(n, op=op, prec=prec)
+            x = to_dev(S, prec)
+            before = plan.residual(x)[0]
+            after = plan.residual(plan.project(x))[0]
+            assert before[2] > 1e-3
+            assert after[2] <= bound, (prec, op, after)
+            plan.destroy()
+
+
+# ------------------------------------------------------------ ABI paths -----
+
+def test_check_finite_flag():
+    eq = eqmod()
+    torch = torch_mod()
+    S = wl.random_field((8, 8, 8), seed=1)
+    S[2, 3, 4, 5] = np.nan
+    plan = eq.plan(8, op="ddo", prec="fp64", flags=["check_finite"])
+    with pytest.raises(eq.EqError) as ei:
+        plan.project(to_dev(S, "fp64"))
+    assert ei.value.code == "EQ_ERR_NONFINITE"
+    S[2, 3, 4, 5] = 0.0
+    plan.project(to_dev(S, "fp64"))
+    plan.destroy()
+
+
+def test_fault_injection_alloc(monkeypatch):
+    eq = eqmod()
+    monkeypatch.setenv("EQ_FAULT_INJECT", "alloc")
+    with pytest.raises(eq.EqError) as ei:
+        eq.plan(16, op="ddo", prec="fp64")
+    assert ei.value.code == "EQ_ERR_NOMEM"
+
+
+def test_aliasing_rejected():
+    eq = eqmod()
+    torch = torch_mod()
+    plan = eq.plan(8, op="ddo", prec="fp64")
+    x = to_dev(wl.random_field((8, 8, 8), seed=2), "fp64")
+    with pytest.raises(eq.EqError) as ei:
+        plan.project(x, torch.empty_like(x), x)
+    assert ei.value.code == "EQ_ERR_ARG"
+    plan.destroy()
+
+
+def test_graph_replay_matches_eager():
+    """Captured graph replays (several, with eager work and syncs between) equal eager runs."""
+    eq = eqmod()
+    torch = torch_mod()
+    s = torch.cuda.Stream()
+    S = wl.config_field("small")
+    with torch.cuda.stream(s):
+        eager = eq.plan(32, op="ddo", prec="fp32")
+        graph = eq.plan(32, op="ddo", prec="fp32", flags=["capture_graph"])
+        x = to_dev(S, "fp32")
+        ref = eager.project(x)
+        out = torch.empty_like(x)
+        rem = torch.empty_like(x)
+        for i in range(4):
+            out.zero_()
+            graph.project(x, out, rem)
+            s.synchronize()
+            assert torch.equal(out, ref), i
+            assert torch.equal(rem, x - ref) or torch.allclose(rem, x - ref, atol=1e-4)
+            _ = eager.project(x * 1.0)         # unrelated eager work between replays
+            torch.cuda.synchronize()
+    eager.destroy()
+    graph.destroy()
+
+
+def test_timing_stats():
+    eq = eqmod()
+    torch = torch_mod()
+    plan = eq.plan(32, op="ddo", prec="fp32")
+    x = to_dev(wl.config_field("small"), "fp32")
+    plan.set_timing(True)
+    for _ in range(3):
+        plan.project(x)
+    st = plan.pass_stats()
+    for name in ("z_r2c", "y_fwd", "x_proj", "y_inv", "z_c2r"):
+        assert st[name]["launches"] == 3 and st[name]["total_ms"] > 0 and st[name]["bytes_per_launch"] > 0
+    plan.reset_stats()
+    assert plan.pass_stats()["x_proj"]["launches"] == 0
+    plan.destroy()
+
+
+# ------------------------------------------------------------- full size ----
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_headline_256_parity(prec):
+    """256^3, 1000 grains with gradients: the benchmark workload, whole-field oracle."""
+    say("headline 256", prec)
+    S = wl.config_field("headline", dtype=np.float32 if prec == "fp32" else np.float64)
+    got, rem = run_project(S, "ddo", prec)
+    ref, _ = O.project(S.astype(np.float64), "ddo")
+    err = rel_l2(got, ref)
+    say("headline rel-L2", prec, err, "max-abs", float(np.abs(got - ref).max()))
+    assert err <= TOL[prec]
