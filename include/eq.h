@@ -128,6 +128,21 @@ eq_status eq_plan_pass_stats(eq_plan_t p, int max, int* count, const char** name
                              long long* launches, double* total_ms, double* bytes_per_launch);
 eq_status eq_plan_reset_stats(eq_plan_t p);
 
+/* Launch-shape tuning (the autotuner's knob; 0 = library default for that knob):
+ * tx_y   x-columns per workgroup of the y passes (must divide nx),
+ * tx_z   real x-columns per workgroup of the z passes (even, must divide nx),
+ * rw_x   (kz, ky) rows per workgroup of the fused x pass,
+ * chunk  planes (field, kz) per chunk of the y -> x -> y sequence, so that a
+ *        chunk's spectrum can stay in the last-level cache between passes
+ *        (0 or -1: one chunk).
+ * Invalid shapes for this grid return EQ_ERR_ARG (EQ_ERR_SIZE if LDS would exceed
+ * the device limit) and leave the plan unchanged.  Results do not depend on the
+ * shapes: every shape computes the same transform with the same arithmetic.
+ * The EQ_TUNE environment variable ("tx_y=16,tx_z=32,rw_x=4,chunk=32") seeds the
+ * tuning at eq_plan.  eq_plan_get_tune writes the shapes in effect to shape4. */
+eq_status eq_plan_tune(eq_plan_t p, int tx_y, int tx_z, int rw_x, int chunk);
+eq_status eq_plan_get_tune(eq_plan_t p, int* shape4);
+
 /* Test hooks (same kernels as eq_project, exposed for per-stage parity):
  * eq_debug_forward: spec_out (device) = the unnormalized forward DFT of s_in as
  *   complex (re, im) pairs laid out (batch, 6, nz/2+1, ny, nx) -- the half spectrum

@@ -34,7 +34,8 @@ STATUS = {0: "EQ_OK", 1: "EQ_ERR_ARG", 2: "EQ_ERR_SIZE", 3: "EQ_ERR_NOMEM", 4: "
 exported_symbols = (
     "eq_plan", "eq_project", "eq_residual", "eq_plan_destroy", "eq_plan_footprint", "eq_status_str",
     "eq_last_error", "eq_plan_set_stream", "eq_plan_set_timing", "eq_plan_pass_stats",
-    "eq_plan_reset_stats", "eq_debug_forward", "eq_debug_project_spectrum", "eq_version",
+    "eq_plan_reset_stats", "eq_debug_forward", "eq_debug_project_spectrum", "eq_version", "eq_plan_tune",
+    "eq_plan_get_tune",
 )
 
 
@@ -79,6 +80,8 @@ def lib() -> ctypes.CDLL:
     L.eq_plan_pass_stats.argtypes = [vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ctypes.c_char_p),
                                      ctypes.POINTER(ctypes.c_longlong), dp, dp]
     L.eq_debug_forward.argtypes = [vp, vp, vp]
+    L.eq_plan_tune.argtypes = [vp, ip, ip, ip, ip]
+    L.eq_plan_get_tune.argtypes = [vp, ctypes.POINTER(ip)]
     L.eq_debug_project_spectrum.argtypes = [vp, vp]
     for name in exported_symbols:
         if name not in ("eq_status_str", "eq_last_error", "eq_version"):
@@ -212,6 +215,15 @@ class Plan:
         """Rebind to `stream` (a torch stream or raw handle; None = torch's current stream)."""
         handle = _stream_handle(stream)
         _check(lib().eq_plan_set_stream(self._h, ctypes.c_void_p(handle) if handle else None), "eq_plan_set_stream")
+
+    def tune(self, tx_y=0, tx_z=0, rw_x=0, chunk=0):
+        """eq_plan_tune: set launch shapes (0 = default); raises EqError if they do not fit."""
+        _check(lib().eq_plan_tune(self._h, int(tx_y), int(tx_z), int(rw_x), int(chunk)), "eq_plan_tune")
+
+    def get_tune(self):
+        out = (ctypes.c_int * 4)()
+        _check(lib().eq_plan_get_tune(self._h, out), "eq_plan_get_tune")
+        return {"tx_y": out[0], "tx_z": out[1], "rw_x": out[2], "chunk": out[3]}
 
     def set_timing(self, enable: bool):
         _check(lib().eq_plan_set_timing(self._h, 1 if enable else 0), "eq_plan_set_timing")

@@ -47,7 +47,10 @@ bool fault_inject_alloc() {
   return v && std::strcmp(v, "alloc") == 0;
 }
 
-// Radix schedule: 8s first, then one 4 (or 4,4 / 2 to finish the power of two), then 3s and 5s.
+// Radix schedules.  Register engine (every radix divides E): powers of two use 8s
+// (E = 8, n <= 64) or 16s (E = 16), with one 2/4/8 to finish; a factor 3 or 5
+// switches to E = 24 or 40 with the power of two in 8s and 4/2.  Edges with both
+// 3 and 5, or fewer than three factors of 2, use the generic engine.
 bool factor_axis(int n, AxisFft* out) {
   if (n < 4 || n > 1024 || (n & 1)) return false;
   int m = n, a = 0, b = 0, c = 0;
@@ -58,6 +61,26 @@ bool factor_axis(int n, AxisFft* out) {
   FftDesc d{};
   d.n = n;
   int k = 0;
+  if (a >= 3 && !(b > 0 && c > 0)) {
+    int E;
+    if (b == 0 && c == 0 && a >= 7) {
+      E = 16;
+      for (int i = 0; i < a / 4; ++i) d.r[k++] = 16;
+      if (a % 4) d.r[k++] = 1 << (a % 4);
+    } else {
+      E = (b > 0) ? 24 : (c > 0 ? 40 : 8);
+      for (int i = 0; i < a / 3; ++i) d.r[k++] = 8;
+      if (a % 3) d.r[k++] = 1 << (a % 3);
+      for (int i = 0; i < b; ++i) d.r[k++] = 3;
+      for (int i = 0; i < c; ++i) d.r[k++] = 5;
+    }
+    if (k > kMaxStages) return false;
+    d.nst = k;
+    out->d = d;
+    out->E = E;
+    out->fast = true;
+    return true;
+  }
   int q = a / 3, r = a % 3;
   if (r == 1 && q >= 1) { q -= 1; r = 4; }     // 2^(3q+1) = 8^(q-1) * 4 * 4
   for (int i = 0; i < q; ++i) d.r[k++] = 8;
@@ -70,6 +93,7 @@ bool factor_axis(int n, AxisFft* out) {
   d.nst = k;
   out->d = d;
   out->E = (n % 8 == 0) ? 8 : ((n % 4 == 0) ? 4 : 2);
+  out->fast = false;
   return true;
 }
 
@@ -90,7 +114,7 @@ eq_status validate(const eq_desc* d) {
                                    ": grid edges must be even, in [4, 1024], with prime factors in {2, 3, 5}");
   // the fused x pass runs the six component lines of a row in one workgroup
   factor_axis(d->nx, &t);
-  if (6 * (d->nx / t.E) > 1024)
+  if (!t.fast && 6 * (d->nx / t.E) > 1024)
     return fail(EQ_ERR_SIZE, "nx = " + std::to_string(d->nx) +
                                  ": six x-lines need more than 1024 threads (nx / largest of 8, 4, 2 dividing it > 170)");
   // total element count must be addressable by the launch grids
@@ -155,6 +179,8 @@ struct eq_plan_s {
   std::vector<hipEvent_t> event_pool;
   long long launches[P_COUNT] = {};
   double total_ms[P_COUNT] = {};
+  double total_bytes[P_COUNT] = {};
+  bool last_removed = false;   // whether the current eq_project writes the removed part
   // graph cache
   struct GraphEntry { const void* in; void* eq; void* rem; hipGraph_t graph; hipGraphExec_t exec; };
   std::vector<GraphEntry> graphs;
@@ -173,7 +199,7 @@ double pass_bytes(const eq_plan_s* p, int pass) {
   switch (pass) {
     case P_Z_R2C: return B * 6 * (M * es + Q);
     case P_Y_FWD: case P_X_PROJ: case P_Y_INV: case P_X_FWD: case P_PROJ_ONLY: return B * 6 * 2 * Q;
-    case P_Z_C2R: return B * 6 * (Q + M * es);
+    case P_Z_C2R: return B * 6 * (Q + M * es) + (p->last_removed ? B * 6 * 2 * M * es : 0.0);
     case P_DIV_DDO: return B * 6 * M * es;
     case P_X_DIV: return B * (6 * Q + 3 * Q);
     case P_Y_INV3: return B * 3 * 2 * Q;
@@ -208,6 +234,7 @@ hipError_t timed(eq_plan_s* p, int pass, F&& launch) {
   e = hipEventRecord(b, p->stream);
   if (e != hipSuccess) return e;
   p->pending.push_back({pass, a, b});
+  p->total_bytes[pass] += pass_bytes(p, pass);
   if (p->pending.size() > 4096) {     // bound the backlog: fold completed records
     (void)hipEventSynchronize(b);
     for (auto& r : p->pending) {
@@ -259,19 +286,57 @@ eq_status dev_alloc(void** ptr, size_t bytes, const char* what) {
   return EQ_OK;
 }
 
-// LDS each pass needs, against the device limit.
-eq_status check_lds(const eq_plan_s* p) {
+// Launch shapes of a tuning against the grid and the device limits.
+eq_status check_shapes(const eq_plan_s* p, const Tune& tn) {
   int limit = 0;
   EQ_HIP(hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device), "hipDeviceGetAttribute");
+  const Geom& g = p->g;
   const int eb = 2 * (int)elem_size(&p->desc);
-  const size_t ly = (size_t)pick_tx_y(p->g, p->ay, eb, p->tune) * p->g.ny * eb;
-  const size_t lz = (size_t)(pick_tx_z(p->g, p->az, eb, p->tune) / 2) * p->g.nz * eb;
-  const size_t lx = (size_t)6 * pick_rw_x(p->g, p->ax, eb, p->tune) * (p->g.nx + 1) * eb;
-  const size_t need = std::max(ly, std::max(lz, lx));
+  const int ty = pick_tx_y(g, p->ay, eb, tn), tz = pick_tx_z(g, p->az, eb, tn), rw = pick_rw_x(g, p->ax, eb, tn);
+  auto round64 = [](int t) { return ((t + 63) / 64) * 64; };
+  const int thy = ty * (g.ny / p->ay.E), thz = (tz / 2) * (g.nz / p->az.E), thx = 6 * rw * (g.nx / p->ax.E);
+  if (ty < 1 || g.nx % ty || round64(thy) > max_threads(p->ay)) return fail(EQ_ERR_ARG, "tx_y does not fit this grid");
+  if (tz < 2 || (tz & 1) || g.nx % tz || round64(thz) > max_threads(p->az))
+    return fail(EQ_ERR_ARG, "tx_z does not fit this grid");
+  if (rw < 1 || round64(thx) > max_threads(p->ax)) return fail(EQ_ERR_ARG, "rw_x does not fit this grid");
+  if (tn.chunk < -1 || tn.chunk > g.batch * g.nzh) return fail(EQ_ERR_ARG, "chunk out of range");
+  const size_t need = std::max(lds_y(g, p->ay, eb, tn), std::max(lds_z(g, p->az, eb, tn), lds_x(g, p->ax, eb, tn)));
   if (need > (size_t)limit)
     return fail(EQ_ERR_SIZE, "grid needs " + std::to_string(need) + " B of LDS per workgroup; device allows " +
                                  std::to_string(limit));
   return EQ_OK;
+}
+
+// Tuning from the environment: EQ_TUNE="tx_y=16,tx_z=32,rw_x=4,chunk=32" (any subset).
+Tune tune_from_env() {
+  Tune t;
+  const char* v = std::getenv("EQ_TUNE");
+  if (!v) return t;
+  std::string s(v);
+  size_t pos = 0;
+  while (pos < s.size()) {
+    size_t end = s.find_first_of(", ", pos);
+    if (end == std::string::npos) end = s.size();
+    const std::string kv = s.substr(pos, end - pos);
+    const size_t eqp = kv.find('=');
+    if (eqp != std::string::npos) {
+      const std::string key = kv.substr(0, eqp);
+      const int val = std::atoi(kv.c_str() + eqp + 1);
+      if (key == "tx_y") t.tx_y = val;
+      else if (key == "tx_z") t.tx_z = val;
+      else if (key == "rw_x") t.rw_x = val;
+      else if (key == "chunk") t.chunk = val;
+    }
+    pos = end + 1;
+  }
+  return t;
+}
+
+// Planes per chunk of the y/x/y sequence (the whole range when chunking is off).
+int chunk_planes(const eq_plan_s* p) {
+  const int total = p->g.batch * p->g.nzh;
+  if (p->tune.chunk > 0) return std::min(p->tune.chunk, total);
+  return total;
 }
 
 template <typename T>
@@ -287,10 +352,18 @@ eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_remove
   const size_t M = field_elems(p);
   EQ_HIP(timed(p, P_Z_R2C, [&] { return launch_z_r2c<T>(static_cast<const T*>(s_in), W, g, p->az, twz, p->tune, s); }),
          "z_r2c launch");
-  EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, 6, p->ay, twy, false, p->tune, s); }), "y_fwd launch");
-  EQ_HIP(timed(p, P_X_PROJ, [&] { return launch_x<T>(W, g, XM_FWD | XM_PROJ | XM_INV, p->ax, twx, p->sym, p->tune, s); }),
-         "x_proj launch");
-  EQ_HIP(timed(p, P_Y_INV, [&] { return launch_y<T>(W, g, 6, p->ay, twy, true, p->tune, s); }), "y_inv launch");
+  const int total = g.batch * g.nzh, cp = chunk_planes(p);
+  for (int pl0 = 0; pl0 < total; pl0 += cp) {
+    const int npl = std::min(cp, total - pl0);
+    EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, pl0, npl, 6, p->ay, twy, false, p->tune, s); }),
+           "y_fwd launch");
+    EQ_HIP(timed(p, P_X_PROJ, [&] {
+             return launch_x<T>(W, g, pl0, npl, XM_FWD | XM_PROJ | XM_INV, p->ax, twx, p->sym, p->tune, s);
+           }),
+           "x_proj launch");
+    EQ_HIP(timed(p, P_Y_INV, [&] { return launch_y<T>(W, g, pl0, npl, 6, p->ay, twy, true, p->tune, s); }),
+           "y_inv launch");
+  }
   EQ_HIP(timed(p, P_Z_C2R, [&] {
            return launch_z_c2r<T>(W, static_cast<T*>(s_eq), 6 * M, M, static_cast<const T*>(s_in),
                                   static_cast<T*>(s_removed), 6, g, p->az, twz, p->tune, s);
@@ -340,10 +413,15 @@ eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out
     }
     EQ_HIP(timed(p, P_Z_R2C, [&] { return launch_z_r2c<T>(static_cast<const T*>(s), W, g, p->az, twz, p->tune, st); }),
            "z_r2c launch");
-    EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, 6, p->ay, twy, false, p->tune, st); }), "y_fwd launch");
-    EQ_HIP(timed(p, P_X_DIV, [&] { return launch_x<T>(W, g, XM_FWD | XM_DIV | XM_INV, p->ax, twx, p->sym, p->tune, st); }),
+    const int total = g.batch * g.nzh;
+    EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, 0, total, 6, p->ay, twy, false, p->tune, st); }),
+           "y_fwd launch");
+    EQ_HIP(timed(p, P_X_DIV, [&] {
+             return launch_x<T>(W, g, 0, total, XM_FWD | XM_DIV | XM_INV, p->ax, twx, p->sym, p->tune, st);
+           }),
            "x_div launch");
-    EQ_HIP(timed(p, P_Y_INV3, [&] { return launch_y<T>(W, g, 3, p->ay, twy, true, p->tune, st); }), "y_inv3 launch");
+    EQ_HIP(timed(p, P_Y_INV3, [&] { return launch_y<T>(W, g, 0, total, 3, p->ay, twy, true, p->tune, st); }),
+           "y_inv3 launch");
     EQ_HIP(timed(p, P_Z_C2R3, [&] {
              return launch_z_c2r<T>(W, dst, dfield, dcomp, nullptr, nullptr, 3, g, p->az, twz, p->tune, st);
            }),
@@ -448,7 +526,8 @@ eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out) {
   p->g = Geom{d->nx, d->ny, d->nz, d->nz / 2 + 1, d->batch};
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }
-  if ((st = check_lds(p)) != EQ_OK) { release(p); return st; }
+  p->tune = tune_from_env();
+  if ((st = check_shapes(p, p->tune)) != EQ_OK) { release(p); return st; }
   if (d->flags & EQ_F_OWN_STREAM) {
     e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
     if (e != hipSuccess) { release(p); return hip_fail(e, "hipStreamCreateWithFlags"); }
@@ -504,6 +583,7 @@ eq_status eq_project(eq_plan_t p, const void* s_in, void* s_eq, void* s_removed)
     return fail(EQ_ERR_ARG, "s_eq partially overlaps s_in");
   DeviceGuard dg(p->device);
   const bool fp64 = p->desc.prec == EQ_FP64;
+  p->last_removed = s_removed != nullptr;
   if (p->desc.flags & EQ_F_CHECK_FINITE) {
     eq_status st = fp64 ? run_check_finite<double>(p, s_in) : run_check_finite<float>(p, s_in);
     if (st != EQ_OK) return st;
@@ -546,6 +626,30 @@ eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_
                                  : run_residual<float>(p, s, norms_host, div_out);
 }
 
+eq_status eq_plan_tune(eq_plan_t p, int tx_y, int tx_z, int rw_x, int chunk) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  Tune t;
+  t.tx_y = tx_y; t.tx_z = tx_z; t.rw_x = rw_x; t.chunk = chunk;
+  if (tx_y < 0 || tx_z < 0 || rw_x < 0) return fail(EQ_ERR_ARG, "negative launch shape");
+  DeviceGuard dg(p->device);
+  eq_status st = check_shapes(p, t);
+  if (st != EQ_OK) return st;
+  EQ_HIP(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  drop_graphs(p);
+  p->tune = t;
+  return EQ_OK;
+}
+
+eq_status eq_plan_get_tune(eq_plan_t p, int* shape4) {
+  if (!p || !shape4) return fail(EQ_ERR_ARG, "null pointer");
+  const int eb = 2 * (int)elem_size(&p->desc);
+  shape4[0] = pick_tx_y(p->g, p->ay, eb, p->tune);
+  shape4[1] = pick_tx_z(p->g, p->az, eb, p->tune);
+  shape4[2] = pick_rw_x(p->g, p->ax, eb, p->tune);
+  shape4[3] = chunk_planes(p);
+  return EQ_OK;
+}
+
 eq_status eq_plan_set_timing(eq_plan_t p, int enable) {
   if (!p) return fail(EQ_ERR_ARG, "null plan");
   p->timing = enable != 0;
@@ -558,7 +662,7 @@ eq_status eq_plan_reset_stats(eq_plan_t p) {
   EQ_HIP(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
   for (auto& r : p->pending) { p->event_pool.push_back(r.a); p->event_pool.push_back(r.b); }
   p->pending.clear();
-  for (int i = 0; i < P_COUNT; ++i) { p->launches[i] = 0; p->total_ms[i] = 0.0; }
+  for (int i = 0; i < P_COUNT; ++i) { p->launches[i] = 0; p->total_ms[i] = 0.0; p->total_bytes[i] = 0.0; }
   return EQ_OK;
 }
 
@@ -583,7 +687,8 @@ eq_status eq_plan_pass_stats(eq_plan_t p, int max, int* count, const char** name
     if (names) names[i] = kPassNames[i];
     if (launches) launches[i] = p->launches[i];
     if (total_ms) total_ms[i] = p->total_ms[i];
-    if (bytes_per_launch) bytes_per_launch[i] = pass_bytes(p, i);
+    if (bytes_per_launch)
+      bytes_per_launch[i] = p->launches[i] ? p->total_bytes[i] / (double)p->launches[i] : pass_bytes(p, i);
   }
   return EQ_OK;
 }
@@ -598,8 +703,9 @@ eq_status eq_debug_forward(eq_plan_t p, const void* s_in, void* spec_out) {
     C* W = static_cast<C*>(spec_out);
     const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
     EQ_HIP(launch_z_r2c<T>(static_cast<const T*>(s_in), W, p->g, p->az, tw + p->g.nx + p->g.ny, p->tune, p->stream), "z_r2c");
-    EQ_HIP(launch_y<T>(W, p->g, 6, p->ay, tw + p->g.nx, false, p->tune, p->stream), "y_fwd");
-    EQ_HIP(launch_x<T>(W, p->g, XM_FWD, p->ax, tw, p->sym, p->tune, p->stream), "x_fwd");
+    const int total = p->g.batch * p->g.nzh;
+    EQ_HIP(launch_y<T>(W, p->g, 0, total, 6, p->ay, tw + p->g.nx, false, p->tune, p->stream), "y_fwd");
+    EQ_HIP(launch_x<T>(W, p->g, 0, total, XM_FWD, p->ax, tw, p->sym, p->tune, p->stream), "x_fwd");
     return EQ_OK;
   };
   return p->desc.prec == EQ_FP64 ? go(double{}) : go(float{});
@@ -612,7 +718,9 @@ eq_status eq_debug_project_spectrum(eq_plan_t p, void* spec) {
     using T = decltype(tag);
     using C = cplx<T>;
     const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
-    EQ_HIP(launch_x<T>(static_cast<C*>(spec), p->g, XM_PROJ, p->ax, tw, p->sym, p->tune, p->stream), "proj_only");
+    EQ_HIP(launch_x<T>(static_cast<C*>(spec), p->g, 0, p->g.batch * p->g.nzh, XM_PROJ, p->ax, tw, p->sym, p->tune,
+                       p->stream),
+           "proj_only");
     return EQ_OK;
   };
   return p->desc.prec == EQ_FP64 ? go(double{}) : go(float{});

@@ -1,18 +1,27 @@
-// eq_fft.hpp -- device-side mixed-radix FFT engine for gfx950.
+// eq_fft.hpp -- mixed-radix FFT engine for gfx950 (device) with a host build of
+// the same arithmetic for emulation on the CPU.
 //
-// A workgroup transforms `nlines` independent lines of length n that live in
-// LDS at lds[line * ls + i * es].  Each line is owned by P = n / E threads
-// (E = nominal elements per thread, a compile-time constant); every stage of
-// radix R in {2, 3, 4, 5, 8} is a Stockham autosort step: each thread loads its
-// butterflies' R inputs at stride n/R, multiplies by the stage twiddles (read
-// from a table generated in FP64 on the device), runs the radix-R DFT in
-// registers, waits at a barrier, then writes the R outputs at stride Ns.  All
-// loads of a stage complete before any store, so the transform is in place in
-// LDS.  Forward uses exp(-2 pi i jk/n), inverse exp(+2 pi i jk/n); neither
-// normalizes.
+// Two engines transform lines of length n (unnormalized; forward uses
+// exp(-2 pi i jk/n), inverse exp(+2 pi i jk/n)):
+//
+// * Register engine (line_fft): the P = n/E threads of a line each own the E
+//   elements p + i*P (i < E).  Every Stockham autosort stage of radix R (R | E)
+//   gives a thread the E/R butterflies j = p + m*P; their inputs j + r*n/R are
+//   exactly elements p + (m + r*E/R)*P, and the outputs of the final stage land
+//   on the same elements.  So the first stage can consume registers loaded
+//   straight from global memory and the last stage can leave its outputs in
+//   registers for a direct store; intermediate stages exchange through LDS.
+// * Generic engine (fft_lines): any radix schedule, every stage staged through
+//   LDS, butterflies distributed with guards.  Used for sizes the register
+//   engine does not schedule (e.g. edges with both 3 and 5 as factors).
+//
+// Stage twiddles come from a table tw[m] = exp(-2 pi i m / n) generated in FP64
+// on the device (rounded once for FP32).
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#define EQ_HD __host__ __device__ __forceinline__
 
 namespace eq {
 
@@ -21,19 +30,26 @@ template <> struct cvec<float>  { using type = float2; };
 template <> struct cvec<double> { using type = double2; };
 template <typename T> using cplx = typename cvec<T>::type;
 
-template <typename T> __device__ __forceinline__ cplx<T> mk(T re, T im) { cplx<T> c; c.x = re; c.y = im; return c; }
-template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C c; c.x = a.x + b.x; c.y = a.y + b.y; return c; }
-template <typename C> __device__ __forceinline__ C csub(C a, C b) { C c; c.x = a.x - b.x; c.y = a.y - b.y; return c; }
-template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+template <typename T> EQ_HD cplx<T> mk(T re, T im) { cplx<T> c; c.x = re; c.y = im; return c; }
+template <typename C> EQ_HD C cadd(C a, C b) { C c; c.x = a.x + b.x; c.y = a.y + b.y; return c; }
+template <typename C> EQ_HD C csub(C a, C b) { C c; c.x = a.x - b.x; c.y = a.y - b.y; return c; }
+template <typename C> EQ_HD C cmul(C a, C b) {
   C c; c.x = a.x * b.x - a.y * b.y; c.y = a.x * b.y + a.y * b.x; return c;
 }
 // multiply by -i (forward) or +i (inverse)
-template <bool INV, typename C> __device__ __forceinline__ C mul_mi(C a) {
+template <bool INV, typename C> EQ_HD C mul_mi(C a) {
   C c;
   if (INV) { c.x = -a.y; c.y = a.x; } else { c.x = a.y; c.y = -a.x; }
   return c;
 }
-template <typename C, typename S> __device__ __forceinline__ C cscale(C a, S s) { C c; c.x = a.x * s; c.y = a.y * s; return c; }
+// multiply by exp(-i theta) (forward) or exp(+i theta) (inverse), given cos and sin of theta
+template <bool INV, typename C, typename S> EQ_HD C rot(C a, S cs, S sn) {
+  C c;
+  if (INV) { c.x = a.x * cs - a.y * sn; c.y = a.x * sn + a.y * cs; }
+  else     { c.x = a.x * cs + a.y * sn; c.y = a.y * cs - a.x * sn; }
+  return c;
+}
+template <typename C, typename S> EQ_HD C cscale(C a, S s) { C c; c.x = a.x * s; c.y = a.y * s; return c; }
 
 constexpr int kMaxStages = 12;
 struct FftDesc {
@@ -47,14 +63,14 @@ struct FftDesc {
 template <int R, bool INV, typename C> struct Dft;
 
 template <bool INV, typename C> struct Dft<2, INV, C> {
-  static __device__ __forceinline__ void run(C* v) {
+  static EQ_HD void run(C* v) {
     C a = v[0], b = v[1];
     v[0] = cadd(a, b); v[1] = csub(a, b);
   }
 };
 
 template <bool INV, typename C> struct Dft<4, INV, C> {
-  static __device__ __forceinline__ void run(C* v) {
+  static EQ_HD void run(C* v) {
     C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
     C t2 = cadd(v[1], v[3]), t3 = mul_mi<INV>(csub(v[1], v[3]));
     v[0] = cadd(t0, t2); v[2] = csub(t0, t2);
@@ -63,23 +79,16 @@ template <bool INV, typename C> struct Dft<4, INV, C> {
 };
 
 template <bool INV, typename C> struct Dft<8, INV, C> {
-  static __device__ __forceinline__ void run(C* v) {
+  static EQ_HD void run(C* v) {
     using T = decltype(v[0].x);
     const T h = (T)0.70710678118654752440084436210484903928;   // sqrt(1/2)
     C e[4] = {v[0], v[2], v[4], v[6]};
     C o[4] = {v[1], v[3], v[5], v[7]};
     Dft<4, INV, C>::run(e);
     Dft<4, INV, C>::run(o);
-    // o[k] *= w8^k, w8 = exp(-+ i pi / 4)
-    C o1, o3;
-    if (INV) {
-      o1.x = h * (o[1].x - o[1].y); o1.y = h * (o[1].x + o[1].y);
-      o3.x = -h * (o[3].x + o[3].y); o3.y = h * (o[3].x - o[3].y);
-    } else {
-      o1.x = h * (o[1].x + o[1].y); o1.y = h * (o[1].y - o[1].x);
-      o3.x = h * (o[3].y - o[3].x); o3.y = -h * (o[3].x + o[3].y);
-    }
-    C o2 = mul_mi<INV>(o[2]);
+    const C o1 = rot<INV>(o[1], h, h);          // w8^1
+    const C o2 = mul_mi<INV>(o[2]);             // w8^2
+    const C o3 = rot<INV>(o[3], -h, h);         // w8^3
     v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
     v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
     v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
@@ -87,8 +96,43 @@ template <bool INV, typename C> struct Dft<8, INV, C> {
   }
 };
 
+// 16 = 4 x 4: inner DFT4 over n1 (stride 4), twiddle w16^(n2 k1), outer DFT4 over n2.
+template <bool INV, typename C> struct Dft<16, INV, C> {
+  static EQ_HD void run(C* v) {
+    using T = decltype(v[0].x);
+    const T c1 = (T)0.92387953251128675612818318939678828682;   // cos(pi/8)
+    const T s1 = (T)0.38268343236508977172845998403039886676;   // sin(pi/8)
+    const T h = (T)0.70710678118654752440084436210484903928;
+    C y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      C a[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+      Dft<4, INV, C>::run(a);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = a[k1];
+    }
+    // twiddles w16^(n2*k1), n2, k1 in 1..3: exponents 1,2,3,2,4,6,3,6,9
+    y[1][1] = rot<INV>(y[1][1], c1, s1);
+    y[1][2] = rot<INV>(y[1][2], h, h);
+    y[1][3] = rot<INV>(y[1][3], s1, c1);
+    y[2][1] = rot<INV>(y[2][1], h, h);
+    y[2][2] = mul_mi<INV>(y[2][2]);
+    y[2][3] = rot<INV>(y[2][3], -h, h);
+    y[3][1] = rot<INV>(y[3][1], s1, c1);
+    y[3][2] = rot<INV>(y[3][2], -h, h);
+    y[3][3] = rot<INV>(y[3][3], -c1, -s1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C b[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      Dft<4, INV, C>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+    }
+  }
+};
+
 template <bool INV, typename C> struct Dft<3, INV, C> {
-  static __device__ __forceinline__ void run(C* v) {
+  static EQ_HD void run(C* v) {
     using T = decltype(v[0].x);
     const T s3 = (T)0.86602540378443864676372317075293618347;   // sin(2 pi / 3)
     C t = cadd(v[1], v[2]);
@@ -102,7 +146,7 @@ template <bool INV, typename C> struct Dft<3, INV, C> {
 };
 
 template <bool INV, typename C> struct Dft<5, INV, C> {
-  static __device__ __forceinline__ void run(C* v) {
+  static EQ_HD void run(C* v) {
     using T = decltype(v[0].x);
     const T c1 = (T)0.30901699437494742410229341718281905886;    // cos(2 pi / 5)
     const T c2 = (T)-0.80901699437494742410229341718281905886;   // cos(4 pi / 5)
@@ -121,9 +165,142 @@ template <bool INV, typename C> struct Dft<5, INV, C> {
   }
 };
 
-// ------------------------------------------------------------------ stage --
+// ------------------------------------------------------- register engine --
 
-// One Stockham stage of radix R on all lines.  tw[m] = exp(-2 pi i m / n).
+// LDS placement of element idx of a line: line * ls + idx * es (+ idx / 16 with skew,
+// which breaks the power-of-two strides of Stockham writes on contiguous lines).
+struct LdsMap {
+  int ls, es, skew;
+  EQ_HD int at(int line, int idx) const { return line * ls + idx * es + (skew ? (idx >> 4) : 0); }
+};
+
+// Stage modes: where the inputs come from and where the outputs go.
+enum StageMode : int { SM_RR = 0, SM_RL = 1, SM_LR = 2, SM_LL = 3 };
+
+// Part A of one stage for one thread: gather, twiddle and DFT its E/R butterflies.
+// RR/LR modes leave outputs in v (final placement), RL writes them to LDS at once,
+// LL leaves them in v in butterfly order for part B (after a barrier).
+template <typename T, int E, int R, bool INV, int MODE>
+EQ_HD void stage_a(cplx<T>* v, cplx<T>* lds, const LdsMap& m, int line, int p, int n, int Ns,
+                   const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  constexpr int MB = E / R;
+  const int P = n / E;
+  const int nb = n / R;
+  const int tws = n / (Ns * R);
+  constexpr bool from_regs = (MODE == SM_RR || MODE == SM_RL);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    const int j = p + mb * P;
+    const int k = j % Ns;
+    C x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = from_regs ? v[mb + r * MB] : lds[m.at(line, j + r * nb)];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C w = tw[r * k * tws];
+        if (INV) w.y = -w.y;
+        x[r] = cmul(x[r], w);
+      }
+    }
+    Dft<R, INV, C>::run(x);
+    // Outputs go straight to their destination: butterfly mb reads and writes only its
+    // own register slots mb + r*MB (RR), and reads LDS when it writes registers (LR, LL).
+    const int o = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (MODE == SM_RR || MODE == SM_LR) v[mb + r * MB] = x[r];      // last stage: o + r*Ns = p + (mb + r*MB)*P
+      else if (MODE == SM_RL) lds[m.at(line, o + r * Ns)] = x[r];
+      else v[mb * R + r] = x[r];
+    }
+  }
+}
+
+// Part B of an LDS-to-LDS stage: scatter the results held in v.
+template <typename T, int E, int R>
+EQ_HD void stage_b(const cplx<T>* v, cplx<T>* lds, const LdsMap& m, int line, int p, int n, int Ns) {
+  constexpr int MB = E / R;
+  const int P = n / E;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    const int j = p + mb * P;
+    const int k = j % Ns;
+    const int o = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[m.at(line, o + r * Ns)] = v[mb * R + r];
+  }
+}
+
+template <int E, int R> struct RadixOk { static constexpr bool value = (E % R) == 0; };
+
+// Mode of stage s of nst given where the line starts (IN_REGS) and must end (OUT_REGS).
+EQ_HD int stage_mode(int s, int nst, bool in_regs, bool out_regs) {
+  const bool fr = (s == 0) && in_regs;
+  const bool tr = (s == nst - 1) && out_regs;
+  return fr ? (tr ? SM_RR : SM_RL) : (tr ? SM_LR : SM_LL);
+}
+
+#ifdef __HIP_DEVICE_COMPILE__
+#define EQ_SYNC() __syncthreads()
+#else
+#define EQ_SYNC() ((void)0)
+#endif
+
+template <typename T, int E, int R, bool INV>
+__device__ __forceinline__ void run_stage(cplx<T>* v, cplx<T>* lds, const LdsMap& m, int line, int p, int n, int Ns,
+                                          const cplx<T>* __restrict__ tw, int mode, bool active) {
+  if constexpr (RadixOk<E, R>::value) {
+    switch (mode) {
+      case SM_RR:
+        if (active) stage_a<T, E, R, INV, SM_RR>(v, lds, m, line, p, n, Ns, tw);
+        break;
+      case SM_RL:
+        if (active) stage_a<T, E, R, INV, SM_RL>(v, lds, m, line, p, n, Ns, tw);
+        EQ_SYNC();
+        break;
+      case SM_LR:
+        if (active) stage_a<T, E, R, INV, SM_LR>(v, lds, m, line, p, n, Ns, tw);
+        break;
+      default:
+        if (active) stage_a<T, E, R, INV, SM_LL>(v, lds, m, line, p, n, Ns, tw);
+        EQ_SYNC();
+        if (active) stage_b<T, E, R>(v, lds, m, line, p, n, Ns);
+        EQ_SYNC();
+        break;
+    }
+  }
+}
+
+// Transform one line per thread group.  IN_REGS: v holds the input elements p + i*P
+// (else the line is in LDS and visible); OUT_REGS: on return v holds the output
+// elements p + i*P (else the output is in LDS, natural order, after a barrier).
+// The caller guarantees no thread still reads LDS when a stage starts writing it:
+// with IN_REGS the first stage writes LDS without a barrier.  Every thread of the
+// block must call this (barriers); inactive threads pass active = false.
+template <typename T, int E, bool INV, bool IN_REGS, bool OUT_REGS>
+__device__ __forceinline__ void line_fft(cplx<T>* v, cplx<T>* lds, const LdsMap& m, int line, int p, const FftDesc& d,
+                                         const cplx<T>* __restrict__ tw, bool active) {
+  int Ns = 1;
+  for (int s = 0; s < d.nst; ++s) {
+    const int R = d.r[s];
+    const int mode = stage_mode(s, d.nst, IN_REGS, OUT_REGS);
+    switch (R) {
+      case 16: run_stage<T, E, 16, INV>(v, lds, m, line, p, d.n, Ns, tw, mode, active); break;
+      case 8: run_stage<T, E, 8, INV>(v, lds, m, line, p, d.n, Ns, tw, mode, active); break;
+      case 4: run_stage<T, E, 4, INV>(v, lds, m, line, p, d.n, Ns, tw, mode, active); break;
+      case 2: run_stage<T, E, 2, INV>(v, lds, m, line, p, d.n, Ns, tw, mode, active); break;
+      case 3: run_stage<T, E, 3, INV>(v, lds, m, line, p, d.n, Ns, tw, mode, active); break;
+      default: run_stage<T, E, 5, INV>(v, lds, m, line, p, d.n, Ns, tw, mode, active); break;
+    }
+    Ns *= R;
+  }
+}
+
+// ------------------------------------------------------- generic engine ---
+
+// One Stockham stage of radix R on all lines held in LDS, butterflies spread over
+// P = n / E threads per line with guards (R need not divide E).
 template <typename T, int E, int R, bool INV>
 __device__ __forceinline__ void fft_stage(cplx<T>* __restrict__ lds, int n, int Ns, int line, int p, int P,
                                           int ls, int es, const cplx<T>* __restrict__ tw, bool active) {
@@ -169,9 +346,8 @@ __device__ __forceinline__ void fft_stage(cplx<T>* __restrict__ lds, int n, int 
   __syncthreads();
 }
 
-// Transform all lines in LDS.  Threads map to (line, p) with line fastest so that
-// consecutive lanes touch consecutive lines; thread tid >= nlines * (n / E) idles
-// but still takes every barrier.
+// Transform all lines in LDS.  Threads map to (line, p) with line fastest; thread
+// tid >= nlines * (n / E) idles but still takes every barrier.
 template <typename T, int E, bool INV>
 __device__ __forceinline__ void fft_lines(cplx<T>* lds, int nlines, int ls, int es, const FftDesc& d,
                                           const cplx<T>* __restrict__ tw, int tid) {

@@ -11,13 +11,16 @@ namespace eq {
 
 // Grid geometry of one plan.  The spectrum workspace W holds, per field, the
 // Hermitian half along z: (batch, 6, nzh = nz/2 + 1, ny, nx) complex.
+// A "plane" is one (field, kz) pair, pl = b * nzh + kz; the y and x passes take
+// a contiguous plane range so the plan can run them chunk by chunk.
 struct Geom {
   int nx, ny, nz, nzh, batch;
 };
 
 struct AxisFft {
   FftDesc d;   // radix schedule of this axis
-  int E;       // nominal elements per thread (2, 4 or 8)
+  int E;       // elements per thread: 8/16/24/40 (register engine) or 2/4/8 (generic engine)
+  bool fast;   // register engine (every radix divides E)
 };
 
 // Launch shape knobs (0 = library default).  The autotuner may set them.
@@ -25,6 +28,7 @@ struct Tune {
   int tx_y = 0;    // x-tile width of the y pass (lines per workgroup)
   int tx_z = 0;    // x-tile width of the z passes (real columns per workgroup, even)
   int rw_x = 0;    // rows per workgroup of the fused x pass
+  int chunk = 0;   // planes per chunk of the y/x/y sequence (0 = library default, -1 = no chunking)
 };
 
 // Modes of the fused x pass.
@@ -46,11 +50,11 @@ hipError_t launch_z_r2c(const T* in, cplx<T>* W, const Geom& g, const AxisFft& a
                         const Tune& tn, hipStream_t s);
 
 template <typename T>
-hipError_t launch_y(cplx<T>* W, const Geom& g, int ncomp, const AxisFft& ay, const cplx<T>* tw_y, bool inv,
-                    const Tune& tn, hipStream_t s);
+hipError_t launch_y(cplx<T>* W, const Geom& g, int pl0, int npl, int ncomp, const AxisFft& ay, const cplx<T>* tw_y,
+                    bool inv, const Tune& tn, hipStream_t s);
 
 template <typename T>
-hipError_t launch_x(cplx<T>* W, const Geom& g, int mode, const AxisFft& ax, const cplx<T>* tw_x,
+hipError_t launch_x(cplx<T>* W, const Geom& g, int pl0, int npl, int mode, const AxisFft& ax, const cplx<T>* tw_x,
                     const double* sym, const Tune& tn, hipStream_t s);
 
 // out(b, c, z, y, x) = out + b * out_field + c * out_comp + (z * ny + y) * nx + x for c < ncomp.
@@ -79,9 +83,13 @@ hipError_t launch_check_finite(const T* in, size_t n, int* flag, hipStream_t s);
 
 hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s);
 
-// Launch shapes the launchers pick (exposed so the plan can size LDS and report).
+// Launch shapes (exposed so the plan can check LDS against the device limit).
 int pick_tx_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);
 int pick_tx_z(const Geom& g, const AxisFft& az, int elem_bytes, const Tune& tn);
 int pick_rw_x(const Geom& g, const AxisFft& ax, int elem_bytes, const Tune& tn);
+int max_threads(const AxisFft& ax);   // workgroup size limit of the engine that serves this axis
+size_t lds_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);
+size_t lds_z(const Geom& g, const AxisFft& az, int elem_bytes, const Tune& tn);
+size_t lds_x(const Geom& g, const AxisFft& ax, int elem_bytes, const Tune& tn);
 
 }  // namespace eq

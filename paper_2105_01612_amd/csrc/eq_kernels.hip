@@ -9,9 +9,15 @@
 //          components of the frequency, inverse DFT along x (one read, one write)
 //   y inv  inverse DFT along y
 //   z_c2r  Hermitian half -> real along z, 1/(nx ny nz), optional removed part
-// Every pass reads its tile into LDS once, transforms it there and writes it
-// once; strided passes tile over contiguous x so every global access is a
-// contiguous run of tile-width elements.
+// Each pass reads its tile once and writes it once.  Strided passes (y, z) tile
+// over contiguous x with lanes running along x, so every global access is a
+// contiguous run of tile-width elements; the x pass reads whole rows.
+//
+// Register-engine kernels (suffix _r): each thread issues all E global loads of
+// its line segment back to back, runs the first FFT stage on them in registers,
+// exchanges through LDS between stages, and stores the last stage's registers
+// directly.  Generic kernels (suffix _g) stage whole tiles through LDS; they
+// serve edges the register engine does not schedule.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,10 +30,9 @@ namespace eq {
 
 namespace {
 
-constexpr int kMaxThreads = 1024;
+constexpr int kMaxThreads = 1024;      // generic-engine workgroups
+constexpr int kMaxFastThreads = 512;   // register-engine workgroups (up to 256 VGPRs per lane)
 constexpr size_t kLdsPreferred = 64 * 1024;
-
-inline int elem_E(int n) { return (n % 8 == 0) ? 8 : ((n % 4 == 0) ? 4 : 2); }
 
 // ------------------------------------------------------------- tables ------
 
@@ -56,85 +61,7 @@ __global__ void k_tables(int nx, int ny, int nz, int op, double h, double* __res
   }
 }
 
-// ------------------------------------------------------------- z r2c -------
-
-struct ZArgs {
-  int nx, ny, nz, tx;      // tx: real x-columns per workgroup (even)
-};
-
-template <typename T, int E>
-__global__ __launch_bounds__(kMaxThreads) void k_z_r2c(const T* __restrict__ in, cplx<T>* __restrict__ W, ZArgs a,
-                                                       FftDesc d, const cplx<T>* __restrict__ tw) {
-  using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int ntx = a.nx / a.tx;
-  int bid = blockIdx.x;
-  const int xt = bid % ntx; bid /= ntx;
-  const int y = bid % a.ny;
-  const int bc = bid / a.ny;                        // b * 6 + c
-  const int np = a.tx >> 1;                         // complex lines (column pairs)
-  const int nz = a.nz, nzh = nz / 2 + 1;
-  const size_t plane = (size_t)a.ny * a.nx;
-  const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
-  for (int u = threadIdx.x; u < nz * np; u += blockDim.x) {
-    const int z = u / np, j = u - z * np;
-    lds[u] = *reinterpret_cast<const C*>(src + (size_t)z * plane + 2 * j);
-  }
-  __syncthreads();
-  fft_lines<T, E, false>(lds, np, 1, np, d, tw, threadIdx.x);
-  C* dst = W + (size_t)bc * nzh * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
-  const T half = (T)0.5;
-  for (int u = threadIdx.x; u < nzh * np; u += blockDim.x) {
-    const int kz = u / np, j = u - kz * np;
-    const C Z = lds[kz * np + j];
-    const C Zm = lds[((nz - kz) % nz) * np + j];
-    // A = (Z + conj Zm) / 2 and B = (Z - conj Zm) / 2i are the spectra of the two columns
-    C A = mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
-    C B = mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half);
-    C* o = dst + (size_t)kz * plane + 2 * j;
-    o[0] = A;
-    o[1] = B;
-  }
-}
-
-// ------------------------------------------------------------- y pass ------
-
-struct YArgs {
-  int nx, ny, nzh, ncomp, tx;
-};
-
-template <typename T, int E, bool INV>
-__global__ __launch_bounds__(kMaxThreads) void k_y(cplx<T>* __restrict__ W, YArgs a, FftDesc d,
-                                                   const cplx<T>* __restrict__ tw) {
-  using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int ntx = a.nx / a.tx;
-  int bid = blockIdx.x;
-  const int xt = bid % ntx; bid /= ntx;
-  const int kz = bid % a.nzh; bid /= a.nzh;
-  const int c = bid % a.ncomp;
-  const int b = bid / a.ncomp;
-  C* base = W + (((size_t)(b * 6 + c) * a.nzh + kz) * a.ny) * a.nx + (size_t)xt * a.tx;
-  const int tx = a.tx;
-  for (int u = threadIdx.x; u < a.ny * tx; u += blockDim.x) {
-    const int y = u / tx, x = u - y * tx;
-    lds[u] = base[(size_t)y * a.nx + x];
-  }
-  __syncthreads();
-  fft_lines<T, E, INV>(lds, tx, 1, tx, d, tw, threadIdx.x);
-  for (int u = threadIdx.x; u < a.ny * tx; u += blockDim.x) {
-    const int y = u / tx, x = u - y * tx;
-    base[(size_t)y * a.nx + x] = lds[u];
-  }
-}
-
-// ------------------------------------------------------------- x pass ------
-
-struct XArgs {
-  int nx, ny, nzh, rows, rw, mode;   // rows = batch * nzh * ny
-};
+// ----------------------------------------------------- per-frequency ops ---
 
 // Projection of one frequency: out = P A P, P = I - n n^T, n = s / |s| formed in FP64.
 // Voigt slots: 0=11 1=22 2=33 3=23 4=13 5=12.
@@ -171,78 +98,102 @@ __device__ __forceinline__ void project_one(cplx<T>* A /*6*/, double sx, double 
   A[5] = upd(a01, n0, n1, b0, b1);
 }
 
+// Divergence of one frequency: r_i = sum_j (i s_j) A_ij, written to slots 0..2.
+template <typename T>
+__device__ __forceinline__ void divergence_one(cplx<T>* A, double sx, double sy, double sz) {
+  using C = cplx<T>;
+  const T s0 = (T)sx, s1 = (T)sy, s2 = (T)sz;
+  const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+  C r3[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const C p = A[idx[i][0]], q = A[idx[i][1]], w = A[idx[i][2]];
+    const T re = s0 * p.x + s1 * q.x + s2 * w.x;
+    const T im = s0 * p.y + s1 * q.y + s2 * w.y;
+    r3[i] = mk<T>(-im, re);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) A[i] = r3[i];
+}
+
+// ------------------------------------------------------------- z passes ----
+
+struct ZArgs {
+  int nx, ny, nz, tx;      // tx: real x-columns per workgroup (even)
+};
+
 template <typename T, int E>
-__global__ __launch_bounds__(kMaxThreads) void k_x(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
-                                                   const cplx<T>* __restrict__ tw, const double* __restrict__ sym) {
+__global__ __launch_bounds__(kMaxFastThreads) void k_z_r2c_r(const T* __restrict__ in, cplx<T>* __restrict__ W, ZArgs a,
+                                                         FftDesc d, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
-  const int nx = a.nx, ls = nx + 1, rw = a.rw;
-  const int row0 = blockIdx.x * rw;
-  const int nrows = min(rw, a.rows - row0);
-  const size_t plane = (size_t)a.ny * nx;
-  const int per_field = a.nzh * a.ny;
-  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
-  auto row_base = [&](int row, int c) -> size_t {
-    const int b = row / per_field;
-    const int rem = row - b * per_field;       // kz * ny + ky
-    return ((size_t)(b * 6 + c) * a.nzh) * plane + (size_t)rem * nx;
-  };
-  // load 6 components x rw rows, contiguous along x
-  for (int c = 0; c < 6; ++c) {
-    for (int u = threadIdx.x; u < rw * nx; u += blockDim.x) {
-      const int r = u / nx, x = u - r * nx;
-      C v = mk<T>((T)0, (T)0);
-      if (r < nrows) v = W[row_base(row0 + r, c) + x];
-      lds[(c * rw + r) * ls + x] = v;
-    }
-  }
-  __syncthreads();
-  if (a.mode & XM_FWD) fft_lines<T, E, false>(lds, 6 * rw, ls, 1, d, tw, threadIdx.x);
-  if (a.mode & (XM_PROJ | XM_DIV)) {
-    const double* symx = sym;
-    const double* symy = sym + nx;
-    const double* symz = sym + nx + a.ny;
-    for (int u = threadIdx.x; u < nrows * nx; u += blockDim.x) {
-      const int r = u / nx, kx = u - r * nx;
-      const int row = row0 + r;
-      const int rem = row % per_field;
-      const int kz = rem / a.ny, ky = rem - kz * a.ny;
-      C A[6];
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int y = bid % a.ny;
+  const int bc = bid / a.ny;                        // b * 6 + c
+  const int np = a.tx >> 1;                         // complex lines (column pairs)
+  const int nz = a.nz, nzh = nz / 2 + 1, P = nz / E;
+  const int line = threadIdx.x % np, p = threadIdx.x / np;
+  const size_t plane = (size_t)a.ny * a.nx;
+  const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx + 2 * line;
+  C v[E];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) A[c] = lds[(c * rw + r) * ls + kx];
-      if (a.mode & XM_PROJ) {
-        project_one<T>(A, symx[kx], symy[ky], symz[kz]);
+  for (int i = 0; i < E; ++i) v[i] = *reinterpret_cast<const C*>(src + (size_t)(p + i * P) * plane);
+  const LdsMap m{1, np, 0};
+  line_fft<T, E, false, true, false>(v, lds, m, line, p, d, tw, true);
+  // separate the two packed columns: A = (Z + conj Zm) / 2, B = (Z - conj Zm) / 2i
+  C* dst = W + (size_t)bc * nzh * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  const T half = (T)0.5;
+  const int nthr = np * P, total = nzh * np;
+  constexpr int NU = E / 2 + 1;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) lds[(c * rw + r) * ls + kx] = A[c];
-      } else {
-        // divergence r_i = sum_j (i s_j) A_ij
-        const T s0 = (T)symx[kx], s1 = (T)symy[ky], s2 = (T)symz[kz];
-        C r3[3];
-        const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const C p = A[idx[i][0]], q = A[idx[i][1]], w = A[idx[i][2]];
-          const T re = s0 * p.x + s1 * q.x + s2 * w.x;
-          const T im = s0 * p.y + s1 * q.y + s2 * w.y;
-          r3[i] = mk<T>(-im, re);
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) lds[(i * rw + r) * ls + kx] = r3[i];
-      }
-    }
-    __syncthreads();
-  }
-  if (a.mode & XM_INV) fft_lines<T, E, true>(lds, ncomp_out * rw, ls, 1, d, tw, threadIdx.x);
-  for (int c = 0; c < ncomp_out; ++c) {
-    for (int u = threadIdx.x; u < nrows * nx; u += blockDim.x) {
-      const int r = u / nx, x = u - r * nx;
-      W[row_base(row0 + r, c) + x] = lds[(c * rw + r) * ls + x];
+  for (int i = 0; i < NU; ++i) {
+    const int u = threadIdx.x + i * nthr;
+    if (u < total) {
+      const int kz = u / np, j = u - kz * np;
+      const C Z = lds[kz * np + j];
+      const C Zm = lds[((nz - kz) % nz) * np + j];
+      C* o = dst + (size_t)kz * plane + 2 * j;
+      o[0] = mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
+      o[1] = mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half);
     }
   }
 }
 
-// ------------------------------------------------------------- z c2r -------
+template <typename T, int E>
+__global__ __launch_bounds__(kMaxThreads) void k_z_r2c_g(const T* __restrict__ in, cplx<T>* __restrict__ W, ZArgs a,
+                                                         FftDesc d, const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int y = bid % a.ny;
+  const int bc = bid / a.ny;
+  const int np = a.tx >> 1;
+  const int nz = a.nz, nzh = nz / 2 + 1;
+  const size_t plane = (size_t)a.ny * a.nx;
+  const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  for (int u = threadIdx.x; u < nz * np; u += blockDim.x) {
+    const int z = u / np, j = u - z * np;
+    lds[u] = *reinterpret_cast<const C*>(src + (size_t)z * plane + 2 * j);
+  }
+  __syncthreads();
+  fft_lines<T, E, false>(lds, np, 1, np, d, tw, threadIdx.x);
+  C* dst = W + (size_t)bc * nzh * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  const T half = (T)0.5;
+  for (int u = threadIdx.x; u < nzh * np; u += blockDim.x) {
+    const int kz = u / np, j = u - kz * np;
+    const C Z = lds[kz * np + j];
+    const C Zm = lds[((nz - kz) % nz) * np + j];
+    C* o = dst + (size_t)kz * plane + 2 * j;
+    o[0] = mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
+    o[1] = mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half);
+  }
+}
 
 struct ZcArgs {
   int nx, ny, nz, tx, ncomp;
@@ -250,8 +201,76 @@ struct ZcArgs {
 };
 
 template <typename T, int E>
-__global__ __launch_bounds__(kMaxThreads) void k_z_c2r(const cplx<T>* __restrict__ W, T* out, const T* in, T* removed,
-                                                       ZcArgs a, FftDesc d, const cplx<T>* __restrict__ tw, T scale) {
+__global__ __launch_bounds__(kMaxFastThreads) void k_z_c2r_r(const cplx<T>* __restrict__ W, T* out, const T* in,
+                                                         T* removed, ZcArgs a, FftDesc d,
+                                                         const cplx<T>* __restrict__ tw, T scale) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int y = bid % a.ny; bid /= a.ny;
+  const int c = bid % a.ncomp;
+  const int b = bid / a.ncomp;
+  const int np = a.tx >> 1;
+  const int nz = a.nz, nzh = nz / 2 + 1, nyq = nz / 2, P = nz / E;
+  const int line = threadIdx.x % np, p = threadIdx.x / np;
+  const size_t plane = (size_t)a.ny * a.nx;
+  const C* src = W + ((size_t)(b * 6 + c) * nzh) * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  const int nthr = np * P, total = nzh * np;
+  constexpr int NU = E / 2 + 1;
+  // pack the two columns of each pair into one complex line: Z = A + i B, Z(-k) = conj A + i conj B
+  C ab[NU][2];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    const int u = threadIdx.x + i * nthr;
+    if (u < total) {
+      const int kz = u / np, j = u - kz * np;
+      const C* s = src + (size_t)kz * plane + 2 * j;
+      ab[i][0] = s[0];
+      ab[i][1] = s[1];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    const int u = threadIdx.x + i * nthr;
+    if (u < total) {
+      const int kz = u / np, j = u - kz * np;
+      C A = ab[i][0], B = ab[i][1];
+      if (kz == 0 || kz == nyq) { A.y = (T)0; B.y = (T)0; }   // self-conjugate planes are real
+      lds[kz * np + j] = mk<T>(A.x - B.y, A.y + B.x);
+      if (kz > 0 && kz < nyq) lds[(nz - kz) * np + j] = mk<T>(A.x + B.y, B.x - A.y);
+    }
+  }
+  __syncthreads();
+  C v[E];
+  const LdsMap m{1, np, 0};
+  line_fft<T, E, true, false, true>(v, lds, m, line, p, d, tw, true);
+  const size_t obase = (size_t)b * a.out_field + (size_t)c * a.out_comp + (size_t)y * a.nx + (size_t)xt * a.tx +
+                       2 * line;
+  if (removed) {
+    C s[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) s[i] = *reinterpret_cast<const C*>(in + obase + (size_t)(p + i * P) * plane);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const C o = mk<T>(v[i].x * scale, v[i].y * scale);
+      const size_t off = obase + (size_t)(p + i * P) * plane;
+      *reinterpret_cast<C*>(removed + off) = mk<T>(s[i].x - o.x, s[i].y - o.y);
+      *reinterpret_cast<C*>(out + off) = o;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      *reinterpret_cast<C*>(out + obase + (size_t)(p + i * P) * plane) = mk<T>(v[i].x * scale, v[i].y * scale);
+  }
+}
+
+template <typename T, int E>
+__global__ __launch_bounds__(kMaxThreads) void k_z_c2r_g(const cplx<T>* __restrict__ W, T* out, const T* in,
+                                                         T* removed, ZcArgs a, FftDesc d,
+                                                         const cplx<T>* __restrict__ tw, T scale) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -269,9 +288,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_z_c2r(const cplx<T>* __restrict
     const int kz = u / np, j = u - kz * np;
     const C* s = src + (size_t)kz * plane + 2 * j;
     C A = s[0], B = s[1];
-    if (kz == 0 || kz == nyq) { A.y = (T)0; B.y = (T)0; }   // self-conjugate planes are real
-    lds[kz * np + j] = mk<T>(A.x - B.y, A.y + B.x);                    // A + i B
-    if (kz > 0 && kz < nyq) lds[(nz - kz) * np + j] = mk<T>(A.x + B.y, B.x - A.y);  // conj A + i conj B
+    if (kz == 0 || kz == nyq) { A.y = (T)0; B.y = (T)0; }
+    lds[kz * np + j] = mk<T>(A.x - B.y, A.y + B.x);
+    if (kz > 0 && kz < nyq) lds[(nz - kz) * np + j] = mk<T>(A.x + B.y, B.x - A.y);
   }
   __syncthreads();
   fft_lines<T, E, true>(lds, np, 1, np, d, tw, threadIdx.x);
@@ -286,6 +305,199 @@ __global__ __launch_bounds__(kMaxThreads) void k_z_c2r(const cplx<T>* __restrict
       *reinterpret_cast<C*>(removed + off) = mk<T>(s.x - o.x, s.y - o.y);
     }
     *reinterpret_cast<C*>(out + off) = o;
+  }
+}
+
+// ------------------------------------------------------------- y pass ------
+
+struct YArgs {
+  int nx, ny, nzh, ncomp, tx, pl0, npl;
+};
+
+__device__ __forceinline__ size_t y_tile_base(const YArgs& a, int& xt_out) {
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int pll = bid % a.npl;
+  const int c = bid / a.npl;
+  const int pl = a.pl0 + pll;
+  const int b = pl / a.nzh, kz = pl - b * a.nzh;
+  xt_out = xt;
+  return (((size_t)(b * 6 + c) * a.nzh + kz) * a.ny) * a.nx + (size_t)xt * a.tx;
+}
+
+template <typename T, int E, bool INV>
+__global__ __launch_bounds__(kMaxFastThreads) void k_y_r(cplx<T>* __restrict__ W, YArgs a, FftDesc d,
+                                                     const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  int xt;
+  C* base = W + y_tile_base(a, xt);
+  const int tx = a.tx, P = a.ny / E;
+  const int line = threadIdx.x % tx, p = threadIdx.x / tx;
+  C* col = base + line;
+  C v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = col[(size_t)(p + i * P) * a.nx];
+  const LdsMap m{1, tx, 0};
+  line_fft<T, E, INV, true, true>(v, lds, m, line, p, d, tw, true);
+#pragma unroll
+  for (int i = 0; i < E; ++i) col[(size_t)(p + i * P) * a.nx] = v[i];
+}
+
+template <typename T, int E, bool INV>
+__global__ __launch_bounds__(kMaxThreads) void k_y_g(cplx<T>* __restrict__ W, YArgs a, FftDesc d,
+                                                     const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  int xt;
+  C* base = W + y_tile_base(a, xt);
+  const int tx = a.tx;
+  for (int u = threadIdx.x; u < a.ny * tx; u += blockDim.x) {
+    const int y = u / tx, x = u - y * tx;
+    lds[u] = base[(size_t)y * a.nx + x];
+  }
+  __syncthreads();
+  fft_lines<T, E, INV>(lds, tx, 1, tx, d, tw, threadIdx.x);
+  for (int u = threadIdx.x; u < a.ny * tx; u += blockDim.x) {
+    const int y = u / tx, x = u - y * tx;
+    base[(size_t)y * a.nx + x] = lds[u];
+  }
+}
+
+// ------------------------------------------------------------- x pass ------
+
+struct XArgs {
+  int nx, ny, nzh, pl0, rows, rw, mode;   // rows = planes in range * ny
+};
+
+__device__ __forceinline__ size_t x_row_base(const XArgs& a, int row, int c, int& kz, int& ky) {
+  const int pl = a.pl0 + row / a.ny;
+  ky = row - (row / a.ny) * a.ny;
+  const int b = pl / a.nzh;
+  kz = pl - b * a.nzh;
+  return (((size_t)(b * 6 + c) * a.nzh + kz) * a.ny + ky) * a.nx;
+}
+
+template <typename T, int E>
+__global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
+                                                     const cplx<T>* __restrict__ tw, const double* __restrict__ sym) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int nx = a.nx, rw = a.rw, P = nx / E;
+  const int p = threadIdx.x % P, line = threadIdx.x / P;   // line = c * rw + r
+  const int c = line / rw, r = line - c * rw;
+  const int row0 = blockIdx.x * rw;
+  const int nrows = min(rw, a.rows - row0);
+  const bool valid = r < nrows;
+  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  const bool active = c < ncomp_out;
+  int kz, ky;
+  const size_t base = valid ? x_row_base(a, row0 + r, c, kz, ky) + p : 0;
+  C v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = valid ? W[base + (size_t)i * P] : mk<T>((T)0, (T)0);
+  const LdsMap m{nx + nx / 16 + 1, 1, 1};
+  if (a.mode & XM_FWD) {
+    line_fft<T, E, false, true, false>(v, lds, m, line, p, d, tw, true);
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds[m.at(line, p + i * P)] = v[i];
+    __syncthreads();
+  }
+  if (a.mode & (XM_PROJ | XM_DIV)) {
+    const double* symx = sym;
+    const double* symy = sym + nx;
+    const double* symz = sym + nx + a.ny;
+    const int nthr = 6 * rw * P, total = nrows * nx;
+    constexpr int NP = (E + 5) / 6;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int u = threadIdx.x + i * nthr;
+      if (u < total) {
+        const int rr = u / nx, kx = u - rr * nx;
+        int qz, qy;
+        (void)x_row_base(a, row0 + rr, 0, qz, qy);
+        C A[6];
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc) A[cc] = lds[m.at(cc * rw + rr, kx)];
+        if (a.mode & XM_PROJ) {
+          project_one<T>(A, symx[kx], symy[qy], symz[qz]);
+#pragma unroll
+          for (int cc = 0; cc < 6; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
+        } else {
+          divergence_one<T>(A, symx[kx], symy[qy], symz[qz]);
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (a.mode & XM_INV) {
+    line_fft<T, E, true, false, true>(v, lds, m, line, p, d, tw, active);
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = lds[m.at(line, p + i * P)];
+  }
+  if (valid && active) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) W[base + (size_t)i * P] = v[i];
+  }
+}
+
+template <typename T, int E>
+__global__ __launch_bounds__(kMaxThreads) void k_x_g(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
+                                                     const cplx<T>* __restrict__ tw, const double* __restrict__ sym) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int nx = a.nx, ls = nx + 1, rw = a.rw;
+  const int row0 = blockIdx.x * rw;
+  const int nrows = min(rw, a.rows - row0);
+  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  int kz, ky;
+  for (int c = 0; c < 6; ++c) {
+    for (int u = threadIdx.x; u < rw * nx; u += blockDim.x) {
+      const int r = u / nx, x = u - r * nx;
+      C v = mk<T>((T)0, (T)0);
+      if (r < nrows) v = W[x_row_base(a, row0 + r, c, kz, ky) + x];
+      lds[(c * rw + r) * ls + x] = v;
+    }
+  }
+  __syncthreads();
+  if (a.mode & XM_FWD) fft_lines<T, E, false>(lds, 6 * rw, ls, 1, d, tw, threadIdx.x);
+  if (a.mode & (XM_PROJ | XM_DIV)) {
+    const double* symx = sym;
+    const double* symy = sym + nx;
+    const double* symz = sym + nx + a.ny;
+    for (int u = threadIdx.x; u < nrows * nx; u += blockDim.x) {
+      const int r = u / nx, kx = u - r * nx;
+      (void)x_row_base(a, row0 + r, 0, kz, ky);
+      C A[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) A[c] = lds[(c * rw + r) * ls + kx];
+      if (a.mode & XM_PROJ) {
+        project_one<T>(A, symx[kx], symy[ky], symz[kz]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) lds[(c * rw + r) * ls + kx] = A[c];
+      } else {
+        divergence_one<T>(A, symx[kx], symy[ky], symz[kz]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lds[(c * rw + r) * ls + kx] = A[c];
+      }
+    }
+    __syncthreads();
+  }
+  if (a.mode & XM_INV) fft_lines<T, E, true>(lds, ncomp_out * rw, ls, 1, d, tw, threadIdx.x);
+  for (int c = 0; c < ncomp_out; ++c) {
+    for (int u = threadIdx.x; u < nrows * nx; u += blockDim.x) {
+      const int r = u / nx, x = u - r * nx;
+      W[x_row_base(a, row0 + r, c, kz, ky) + x] = lds[(c * rw + r) * ls + x];
+    }
   }
 }
 
@@ -304,8 +516,8 @@ __device__ __forceinline__ void block_reduce_record(double* v, double* sh /* kRe
 #pragma unroll
       for (int k = 0; k < kRedWidth; ++k) {
         const double o = sh[k * kRedThreads + t + stride];
-        double& m = sh[k * kRedThreads + t];
-        m = (k == 1) ? fmax(m, o) : m + o;
+        double& mm = sh[k * kRedThreads + t];
+        mm = (k == 1) ? fmax(mm, o) : mm + o;
       }
     }
     __syncthreads();
@@ -342,8 +554,8 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
     const size_t ym = (y == 0) ? v + (size_t)(a.ny - 1) * sy : v - sy;
     const size_t zp = (z + 1 == a.nz) ? v + sz - (size_t)a.nz * sz : v + sz;
     const size_t zm = (z == 0) ? v + (size_t)(a.nz - 1) * sz : v - sz;
-    auto D = [&](int c, size_t p, size_t m) -> double {
-      return ((double)F[c * M + p] - (double)F[c * M + m]) * a.inv2h;
+    auto D = [&](int c, size_t pp, size_t mm) -> double {
+      return ((double)F[c * M + pp] - (double)F[c * M + mm]) * a.inv2h;
     };
     // r_x = d_x S11 + d_y S12 + d_z S13, etc. (slots 0=11 1=22 2=33 3=23 4=13 5=12)
     const double r0 = D(0, xp, xm) + D(5, yp, ym) + D(4, zp, zm);
@@ -365,9 +577,9 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
   }
   block_reduce_record(acc, sh);
   if (threadIdx.x == 0) {
-    double* p = partials + ((size_t)b * gridDim.x + blockIdx.x) * kRedWidth;
+    double* pp = partials + ((size_t)b * gridDim.x + blockIdx.x) * kRedWidth;
 #pragma unroll
-    for (int k = 0; k < kRedWidth; ++k) p[k] = acc[k];
+    for (int k = 0; k < kRedWidth; ++k) pp[k] = acc[k];
   }
 }
 
@@ -401,9 +613,9 @@ __global__ __launch_bounds__(kRedThreads) void k_div_stats(const T* __restrict__
   }
   block_reduce_record(acc, sh);
   if (threadIdx.x == 0) {
-    double* p = partials + ((size_t)b * gridDim.x + blockIdx.x) * kRedWidth;
+    double* pp = partials + ((size_t)b * gridDim.x + blockIdx.x) * kRedWidth;
 #pragma unroll
-    for (int k = 0; k < kRedWidth; ++k) p[k] = acc[k];
+    for (int k = 0; k < kRedWidth; ++k) pp[k] = acc[k];
   }
 }
 
@@ -415,9 +627,9 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __re
 #pragma unroll
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
   for (int i = threadIdx.x; i < nblk; i += kRedThreads) {
-    const double* p = partials + ((size_t)b * nblk + i) * kRedWidth;
+    const double* pp = partials + ((size_t)b * nblk + i) * kRedWidth;
 #pragma unroll
-    for (int k = 0; k < kRedWidth; ++k) acc[k] = (k == 1) ? fmax(acc[k], p[k]) : acc[k] + p[k];
+    for (int k = 0; k < kRedWidth; ++k) acc[k] = (k == 1) ? fmax(acc[k], pp[k]) : acc[k] + pp[k];
   }
   block_reduce_record(acc, sh);
   if (threadIdx.x == 0) {
@@ -443,13 +655,30 @@ size_t csize() { return sizeof(cplx<T>); }
 
 int round_threads(int t) { return t < 64 ? 64 : ((t + 63) / 64) * 64; }
 
+int largest_pow2_divisor_le(int n, int cap) {
+  int t = 1;
+  while (t * 2 <= cap && n % (t * 2) == 0) t *= 2;
+  return t;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- shapes ------
+// Register-engine shapes aim at ~256 threads per workgroup (several workgroups per
+// CU so load, transform and store phases of different workgroups overlap) with
+// tiles at least 128 bytes wide along x.
 
 int pick_tx_y(const Geom& g, const AxisFft& ay, int eb, const Tune& tn) {
   if (tn.tx_y > 0) return tn.tx_y;
   const int P = g.ny / ay.E;
+  if (ay.fast) {
+    const int min_tx = 128 / eb;
+    int want = 256 / P;
+    if (want < min_tx) want = min_tx;
+    int tx = largest_pow2_divisor_le(g.nx, want > 64 ? 64 : want);
+    while (tx > 1 && (tx * P > kMaxFastThreads || (size_t)tx * g.ny * eb > kLdsPreferred)) tx >>= 1;
+    return tx;
+  }
   int tx = 64;
   while (tx > 1 && (g.nx % tx != 0 || tx * P > kMaxThreads || (size_t)tx * g.ny * eb > kLdsPreferred)) tx >>= 1;
   return tx;
@@ -458,6 +687,14 @@ int pick_tx_y(const Geom& g, const AxisFft& ay, int eb, const Tune& tn) {
 int pick_tx_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
   if (tn.tx_z > 0) return tn.tx_z;
   const int P = g.nz / az.E;
+  if (az.fast) {
+    const int min_np = 128 / eb;
+    int want = 256 / P;
+    if (want < min_np) want = min_np;
+    int tx = 2 * largest_pow2_divisor_le(g.nx / 2, want > 64 ? 64 : want);
+    while (tx > 2 && ((tx / 2) * P > kMaxFastThreads || (size_t)(tx / 2) * g.nz * eb > kLdsPreferred)) tx >>= 1;
+    return tx;
+  }
   int tx = 128;
   while (tx > 2 && (g.nx % tx != 0 || (tx / 2) * P > kMaxThreads || (size_t)(tx / 2) * g.nz * eb > kLdsPreferred))
     tx >>= 1;
@@ -467,9 +704,29 @@ int pick_tx_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
 int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
   if (tn.rw_x > 0) return tn.rw_x;
   const int P = g.nx / ax.E;
+  if (ax.fast) {
+    const int ls = g.nx + g.nx / 16 + 1;
+    int rw = 384 / (6 * P);
+    if (rw < 1) rw = 1;
+    while (rw > 1 && (6 * rw * P > kMaxFastThreads || (size_t)6 * rw * ls * eb > kLdsPreferred)) --rw;
+    return rw;
+  }
   int rw = 16;
   while (rw > 1 && (6 * rw * P > kMaxThreads || (size_t)6 * rw * (g.nx + 1) * eb > kLdsPreferred)) --rw;
   return rw;
+}
+
+int max_threads(const AxisFft& ax) { return ax.fast ? kMaxFastThreads : kMaxThreads; }
+
+size_t lds_y(const Geom& g, const AxisFft& ay, int eb, const Tune& tn) {
+  return (size_t)pick_tx_y(g, ay, eb, tn) * g.ny * eb;
+}
+size_t lds_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
+  return (size_t)(pick_tx_z(g, az, eb, tn) / 2) * g.nz * eb;
+}
+size_t lds_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
+  const int ls = ax.fast ? g.nx + g.nx / 16 + 1 : g.nx + 1;
+  return (size_t)6 * pick_rw_x(g, ax, eb, tn) * ls * eb;
 }
 
 // ----------------------------------------------------------- launchers -----
@@ -480,58 +737,76 @@ hipError_t launch_tables(const Geom& g, int op, double h, double* sym, double2* 
   return hipGetLastError();
 }
 
+#define EQ_FAST_E_SWITCH(E_, BODY) \
+  switch (E_) {                    \
+    case 8: { constexpr int EE = 8; BODY; } break;   \
+    case 16: { constexpr int EE = 16; BODY; } break; \
+    case 24: { constexpr int EE = 24; BODY; } break; \
+    default: { constexpr int EE = 40; BODY; } break; \
+  }
+#define EQ_GEN_E_SWITCH(E_, BODY)  \
+  switch (E_) {                    \
+    case 8: { constexpr int EE = 8; BODY; } break;   \
+    case 4: { constexpr int EE = 4; BODY; } break;   \
+    default: { constexpr int EE = 2; BODY; } break;  \
+  }
+
 template <typename T>
 hipError_t launch_z_r2c(const T* in, cplx<T>* W, const Geom& g, const AxisFft& az, const cplx<T>* tw_z,
                         const Tune& tn, hipStream_t s) {
   const int eb = (int)csize<T>();
   const int tx = pick_tx_z(g, az, eb, tn);
   ZArgs a{g.nx, g.ny, g.nz, tx};
-  const int threads = round_threads((tx / 2) * (g.nz / az.E));
-  const size_t lds = (size_t)(tx / 2) * g.nz * eb;
+  const size_t lds = lds_z(g, az, eb, tn);
   const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.ny * g.batch * 6));
-  switch (az.E) {
-    case 8: hipLaunchKernelGGL((k_z_r2c<T, 8>), grid, dim3(threads), lds, s, in, W, a, az.d, tw_z); break;
-    case 4: hipLaunchKernelGGL((k_z_r2c<T, 4>), grid, dim3(threads), lds, s, in, W, a, az.d, tw_z); break;
-    default: hipLaunchKernelGGL((k_z_r2c<T, 2>), grid, dim3(threads), lds, s, in, W, a, az.d, tw_z); break;
+  const int P = g.nz / az.E;
+  if (az.fast) {
+    const dim3 block((tx / 2) * P);
+    EQ_FAST_E_SWITCH(az.E, hipLaunchKernelGGL((k_z_r2c_r<T, EE>), grid, block, lds, s, in, W, a, az.d, tw_z));
+  } else {
+    const dim3 block(round_threads((tx / 2) * P));
+    EQ_GEN_E_SWITCH(az.E, hipLaunchKernelGGL((k_z_r2c_g<T, EE>), grid, block, lds, s, in, W, a, az.d, tw_z));
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_y(cplx<T>* W, const Geom& g, int ncomp, const AxisFft& ay, const cplx<T>* tw_y, bool inv,
-                    const Tune& tn, hipStream_t s) {
+hipError_t launch_y(cplx<T>* W, const Geom& g, int pl0, int npl, int ncomp, const AxisFft& ay, const cplx<T>* tw_y,
+                    bool inv, const Tune& tn, hipStream_t s) {
   const int eb = (int)csize<T>();
   const int tx = pick_tx_y(g, ay, eb, tn);
-  YArgs a{g.nx, g.ny, g.nzh, ncomp, tx};
-  const int threads = round_threads(tx * (g.ny / ay.E));
-  const size_t lds = (size_t)tx * g.ny * eb;
-  const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.nzh * ncomp * g.batch));
-#define EQ_LAUNCH_Y(EE)                                                                                    \
-  if (inv) hipLaunchKernelGGL((k_y<T, EE, true>), grid, dim3(threads), lds, s, W, a, ay.d, tw_y);         \
-  else hipLaunchKernelGGL((k_y<T, EE, false>), grid, dim3(threads), lds, s, W, a, ay.d, tw_y);
-  switch (ay.E) {
-    case 8: EQ_LAUNCH_Y(8) break;
-    case 4: EQ_LAUNCH_Y(4) break;
-    default: EQ_LAUNCH_Y(2) break;
+  YArgs a{g.nx, g.ny, g.nzh, ncomp, tx, pl0, npl};
+  const size_t lds = lds_y(g, ay, eb, tn);
+  const dim3 grid((unsigned)((size_t)(g.nx / tx) * npl * ncomp));
+  const int P = g.ny / ay.E;
+  if (ay.fast) {
+    const dim3 block(tx * P);
+    if (inv) { EQ_FAST_E_SWITCH(ay.E, hipLaunchKernelGGL((k_y_r<T, EE, true>), grid, block, lds, s, W, a, ay.d, tw_y)); }
+    else { EQ_FAST_E_SWITCH(ay.E, hipLaunchKernelGGL((k_y_r<T, EE, false>), grid, block, lds, s, W, a, ay.d, tw_y)); }
+  } else {
+    const dim3 block(round_threads(tx * P));
+    if (inv) { EQ_GEN_E_SWITCH(ay.E, hipLaunchKernelGGL((k_y_g<T, EE, true>), grid, block, lds, s, W, a, ay.d, tw_y)); }
+    else { EQ_GEN_E_SWITCH(ay.E, hipLaunchKernelGGL((k_y_g<T, EE, false>), grid, block, lds, s, W, a, ay.d, tw_y)); }
   }
-#undef EQ_LAUNCH_Y
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_x(cplx<T>* W, const Geom& g, int mode, const AxisFft& ax, const cplx<T>* tw_x, const double* sym,
-                    const Tune& tn, hipStream_t s) {
+hipError_t launch_x(cplx<T>* W, const Geom& g, int pl0, int npl, int mode, const AxisFft& ax, const cplx<T>* tw_x,
+                    const double* sym, const Tune& tn, hipStream_t s) {
   const int eb = (int)csize<T>();
   const int rw = pick_rw_x(g, ax, eb, tn);
-  const int rows = g.batch * g.nzh * g.ny;
-  XArgs a{g.nx, g.ny, g.nzh, rows, rw, mode};
-  const int threads = round_threads(6 * rw * (g.nx / ax.E));
-  const size_t lds = (size_t)6 * rw * (g.nx + 1) * eb;
+  const int rows = npl * g.ny;
+  XArgs a{g.nx, g.ny, g.nzh, pl0, rows, rw, mode};
+  const size_t lds = lds_x(g, ax, eb, tn);
   const dim3 grid((unsigned)((rows + rw - 1) / rw));
-  switch (ax.E) {
-    case 8: hipLaunchKernelGGL((k_x<T, 8>), grid, dim3(threads), lds, s, W, a, ax.d, tw_x, sym); break;
-    case 4: hipLaunchKernelGGL((k_x<T, 4>), grid, dim3(threads), lds, s, W, a, ax.d, tw_x, sym); break;
-    default: hipLaunchKernelGGL((k_x<T, 2>), grid, dim3(threads), lds, s, W, a, ax.d, tw_x, sym); break;
+  const int P = g.nx / ax.E;
+  if (ax.fast) {
+    const dim3 block(6 * rw * P);
+    EQ_FAST_E_SWITCH(ax.E, hipLaunchKernelGGL((k_x_r<T, EE>), grid, block, lds, s, W, a, ax.d, tw_x, sym));
+  } else {
+    const dim3 block(round_threads(6 * rw * P));
+    EQ_GEN_E_SWITCH(ax.E, hipLaunchKernelGGL((k_x_g<T, EE>), grid, block, lds, s, W, a, ax.d, tw_x, sym));
   }
   return hipGetLastError();
 }
@@ -543,14 +818,18 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
   const int eb = (int)csize<T>();
   const int tx = pick_tx_z(g, az, eb, tn);
   ZcArgs a{g.nx, g.ny, g.nz, tx, ncomp, out_field, out_comp};
-  const int threads = round_threads((tx / 2) * (g.nz / az.E));
-  const size_t lds = (size_t)(tx / 2) * g.nz * eb;
+  const size_t lds = lds_z(g, az, eb, tn);
   const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.ny * ncomp * g.batch));
   const T scale = (T)(1.0 / ((double)g.nx * (double)g.ny * (double)g.nz));
-  switch (az.E) {
-    case 8: hipLaunchKernelGGL((k_z_c2r<T, 8>), grid, dim3(threads), lds, s, W, out, in, removed, a, az.d, tw_z, scale); break;
-    case 4: hipLaunchKernelGGL((k_z_c2r<T, 4>), grid, dim3(threads), lds, s, W, out, in, removed, a, az.d, tw_z, scale); break;
-    default: hipLaunchKernelGGL((k_z_c2r<T, 2>), grid, dim3(threads), lds, s, W, out, in, removed, a, az.d, tw_z, scale); break;
+  const int P = g.nz / az.E;
+  if (az.fast) {
+    const dim3 block((tx / 2) * P);
+    EQ_FAST_E_SWITCH(az.E, hipLaunchKernelGGL((k_z_c2r_r<T, EE>), grid, block, lds, s, W, out, in, removed, a, az.d,
+                                              tw_z, scale));
+  } else {
+    const dim3 block(round_threads((tx / 2) * P));
+    EQ_GEN_E_SWITCH(az.E, hipLaunchKernelGGL((k_z_c2r_g<T, EE>), grid, block, lds, s, W, out, in, removed, a, az.d,
+                                             tw_z, scale));
   }
   return hipGetLastError();
 }
@@ -591,18 +870,18 @@ hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s) {
 
 // ------------------------------------------------------ instantiations -----
 
-#define EQ_INSTANTIATE(T)                                                                                         \
-  template hipError_t launch_z_r2c<T>(const T*, cplx<T>*, const Geom&, const AxisFft&, const cplx<T>*,          \
-                                      const Tune&, hipStream_t);                                                  \
-  template hipError_t launch_y<T>(cplx<T>*, const Geom&, int, const AxisFft&, const cplx<T>*, bool, const Tune&, \
-                                  hipStream_t);                                                                   \
-  template hipError_t launch_x<T>(cplx<T>*, const Geom&, int, const AxisFft&, const cplx<T>*, const double*,     \
-                                  const Tune&, hipStream_t);                                                      \
-  template hipError_t launch_z_c2r<T>(const cplx<T>*, T*, size_t, size_t, const T*, T*, int, const Geom&,        \
-                                      const AxisFft&, const cplx<T>*, const Tune&, hipStream_t);                  \
-  template hipError_t launch_div_ddo<T>(const T*, T*, double*, int, const Geom&, double, hipStream_t);          \
-  template hipError_t launch_div_stats<T>(const T*, size_t, size_t, const T*, double*, int, const Geom&,        \
-                                          hipStream_t);                                                           \
+#define EQ_INSTANTIATE(T)                                                                                          \
+  template hipError_t launch_z_r2c<T>(const T*, cplx<T>*, const Geom&, const AxisFft&, const cplx<T>*,           \
+                                      const Tune&, hipStream_t);                                                   \
+  template hipError_t launch_y<T>(cplx<T>*, const Geom&, int, int, int, const AxisFft&, const cplx<T>*, bool,     \
+                                  const Tune&, hipStream_t);                                                       \
+  template hipError_t launch_x<T>(cplx<T>*, const Geom&, int, int, int, const AxisFft&, const cplx<T>*,          \
+                                  const double*, const Tune&, hipStream_t);                                        \
+  template hipError_t launch_z_c2r<T>(const cplx<T>*, T*, size_t, size_t, const T*, T*, int, const Geom&,         \
+                                      const AxisFft&, const cplx<T>*, const Tune&, hipStream_t);                   \
+  template hipError_t launch_div_ddo<T>(const T*, T*, double*, int, const Geom&, double, hipStream_t);           \
+  template hipError_t launch_div_stats<T>(const T*, size_t, size_t, const T*, double*, int, const Geom&,         \
+                                          hipStream_t);                                                            \
   template hipError_t launch_check_finite<T>(const T*, size_t, int*, hipStream_t);
 
 EQ_INSTANTIATE(float)
