@@ -48,10 +48,10 @@ bool fault_inject_alloc() {
 }
 
 // Radix schedules.  Register engine (every radix divides E): powers of two use 8s
-// (E = 8, n <= 64) or 16s (E = 16), with one 2/4/8 to finish; a factor 3 or 5
+// (E = 8) or, with `wide` and n >= 128, 16s (E = 16), with one 2/4/8 to finish; a factor 3 or 5
 // switches to E = 24 or 40 with the power of two in 8s and 4/2.  Edges with both
 // 3 and 5, or fewer than three factors of 2, use the generic engine.
-bool factor_axis(int n, AxisFft* out) {
+bool factor_axis(int n, AxisFft* out, bool wide = false) {
   if (n < 4 || n > 1024 || (n & 1)) return false;
   int m = n, a = 0, b = 0, c = 0;
   while (m % 2 == 0) { m /= 2; ++a; }
@@ -63,7 +63,11 @@ bool factor_axis(int n, AxisFft* out) {
   int k = 0;
   if (a >= 3 && !(b > 0 && c > 0)) {
     int E;
-    if (b == 0 && c == 0 && a >= 7) {
+    // E = 16 (radix-16 stages) only where asked: the y passes run best with it, the
+    // z and x passes with E = 8 (fewer registers per lane).  EQ_FFT_E16=0/1 overrides.
+    const char* e16 = std::getenv("EQ_FFT_E16");
+    const bool use16 = e16 ? (e16[0] == '1') : wide;
+    if (b == 0 && c == 0 && a >= 7 && use16) {
       E = 16;
       for (int i = 0; i < a / 4; ++i) d.r[k++] = 16;
       if (a % 4) d.r[k++] = 1 << (a % 4);
@@ -223,7 +227,7 @@ hipEvent_t get_event(eq_plan_s* p) {
 
 // Bracket one launch with events when timing is on.
 template <typename F>
-hipError_t timed(eq_plan_s* p, int pass, F&& launch) {
+hipError_t timed(eq_plan_s* p, int pass, F&& launch, double frac = 1.0) {
   if (!p->timing) return launch();
   hipEvent_t a = get_event(p), b = get_event(p);
   if (!a || !b) return hipErrorOutOfMemory;
@@ -234,7 +238,7 @@ hipError_t timed(eq_plan_s* p, int pass, F&& launch) {
   e = hipEventRecord(b, p->stream);
   if (e != hipSuccess) return e;
   p->pending.push_back({pass, a, b});
-  p->total_bytes[pass] += pass_bytes(p, pass);
+  p->total_bytes[pass] += frac * pass_bytes(p, pass);
   if (p->pending.size() > 4096) {     // bound the backlog: fold completed records
     (void)hipEventSynchronize(b);
     for (auto& r : p->pending) {
@@ -294,7 +298,8 @@ eq_status check_shapes(const eq_plan_s* p, const Tune& tn) {
   const int eb = 2 * (int)elem_size(&p->desc);
   const int ty = pick_tx_y(g, p->ay, eb, tn), tz = pick_tx_z(g, p->az, eb, tn), rw = pick_rw_x(g, p->ax, eb, tn);
   auto round64 = [](int t) { return ((t + 63) / 64) * 64; };
-  const int thy = ty * (g.ny / p->ay.E), thz = (tz / 2) * (g.nz / p->az.E), thx = 6 * rw * (g.nx / p->ax.E);
+  const int thy = ty * (g.ny / p->ay.E), thz = (tz / 2) * (g.nz / p->az.E);
+  const int thx = (x_threads_per_row(p->ax, eb)) * rw;
   if (ty < 1 || g.nx % ty || round64(thy) > max_threads(p->ay)) return fail(EQ_ERR_ARG, "tx_y does not fit this grid");
   if (tz < 2 || (tz & 1) || g.nx % tz || round64(thz) > max_threads(p->az))
     return fail(EQ_ERR_ARG, "tx_z does not fit this grid");
@@ -355,13 +360,15 @@ eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_remove
   const int total = g.batch * g.nzh, cp = chunk_planes(p);
   for (int pl0 = 0; pl0 < total; pl0 += cp) {
     const int npl = std::min(cp, total - pl0);
-    EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, pl0, npl, 6, p->ay, twy, false, p->tune, s); }),
+    const double frac = (double)npl / (double)total;    // share of the field's bytes in this launch
+    EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, pl0, npl, 6, p->ay, twy, false, p->tune, s); }, frac),
            "y_fwd launch");
-    EQ_HIP(timed(p, P_X_PROJ, [&] {
-             return launch_x<T>(W, g, pl0, npl, XM_FWD | XM_PROJ | XM_INV, p->ax, twx, p->sym, p->tune, s);
-           }),
+    EQ_HIP(timed(
+               p, P_X_PROJ,
+               [&] { return launch_x<T>(W, g, pl0, npl, XM_FWD | XM_PROJ | XM_INV, p->ax, twx, p->sym, p->tune, s); },
+               frac),
            "x_proj launch");
-    EQ_HIP(timed(p, P_Y_INV, [&] { return launch_y<T>(W, g, pl0, npl, 6, p->ay, twy, true, p->tune, s); }),
+    EQ_HIP(timed(p, P_Y_INV, [&] { return launch_y<T>(W, g, pl0, npl, 6, p->ay, twy, true, p->tune, s); }, frac),
            "y_inv launch");
   }
   EQ_HIP(timed(p, P_Z_C2R, [&] {
@@ -520,9 +527,9 @@ eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out) {
   eq_plan_s* p = new (std::nothrow) eq_plan_s();
   if (!p) return fail(EQ_ERR_NOMEM, "host allocation failed");
   p->desc = *d;
-  factor_axis(d->nx, &p->ax);
-  factor_axis(d->ny, &p->ay);
-  factor_axis(d->nz, &p->az);
+  factor_axis(d->nx, &p->ax, false);
+  factor_axis(d->ny, &p->ay, true);
+  factor_axis(d->nz, &p->az, false);
   p->g = Geom{d->nx, d->ny, d->nz, d->nz / 2 + 1, d->batch};
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }

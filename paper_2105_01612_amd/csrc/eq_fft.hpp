@@ -174,6 +174,9 @@ struct LdsMap {
   EQ_HD int at(int line, int idx) const { return line * ls + idx * es + (skew ? (idx >> 4) : 0); }
 };
 
+// j mod Ns; Ns is a power of two except after a radix-3/5 stage (those come last in a schedule).
+EQ_HD int mod_ns(int j, int Ns) { return (Ns & (Ns - 1)) == 0 ? (j & (Ns - 1)) : (j % Ns); }
+
 // Stage modes: where the inputs come from and where the outputs go.
 enum StageMode : int { SM_RR = 0, SM_RL = 1, SM_LR = 2, SM_LL = 3 };
 
@@ -192,7 +195,7 @@ EQ_HD void stage_a(cplx<T>* v, cplx<T>* lds, const LdsMap& m, int line, int p, i
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     const int j = p + mb * P;
-    const int k = j % Ns;
+    const int k = mod_ns(j, Ns);
     C x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = from_regs ? v[mb + r * MB] : lds[m.at(line, j + r * nb)];
@@ -225,7 +228,7 @@ EQ_HD void stage_b(const cplx<T>* v, cplx<T>* lds, const LdsMap& m, int line, in
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     const int j = p + mb * P;
-    const int k = j % Ns;
+    const int k = mod_ns(j, Ns);
     const int o = (j - k) * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) lds[m.at(line, o + r * Ns)] = v[mb * R + r];
@@ -296,6 +299,105 @@ __device__ __forceinline__ void line_fft(cplx<T>* v, cplx<T>* lds, const LdsMap&
     Ns *= R;
   }
 }
+
+// NL lines per thread (lines line0 + l * lstride, l < NL), sharing every barrier.
+template <typename T, int E, int R, bool INV, int NL>
+__device__ __forceinline__ void run_stage_multi(cplx<T> (*v)[E], cplx<T>* lds, const LdsMap& m, int line0,
+                                                int lstride, int p, int n, int Ns, const cplx<T>* __restrict__ tw,
+                                                int mode) {
+  if constexpr (RadixOk<E, R>::value) {
+    switch (mode) {
+      case SM_RR:
+#pragma unroll
+        for (int l = 0; l < NL; ++l) stage_a<T, E, R, INV, SM_RR>(v[l], lds, m, line0 + l * lstride, p, n, Ns, tw);
+        break;
+      case SM_RL:
+#pragma unroll
+        for (int l = 0; l < NL; ++l) stage_a<T, E, R, INV, SM_RL>(v[l], lds, m, line0 + l * lstride, p, n, Ns, tw);
+        EQ_SYNC();
+        break;
+      case SM_LR:
+#pragma unroll
+        for (int l = 0; l < NL; ++l) stage_a<T, E, R, INV, SM_LR>(v[l], lds, m, line0 + l * lstride, p, n, Ns, tw);
+        break;
+      default:
+#pragma unroll
+        for (int l = 0; l < NL; ++l) stage_a<T, E, R, INV, SM_LL>(v[l], lds, m, line0 + l * lstride, p, n, Ns, tw);
+        EQ_SYNC();
+#pragma unroll
+        for (int l = 0; l < NL; ++l) stage_b<T, E, R>(v[l], lds, m, line0 + l * lstride, p, n, Ns);
+        EQ_SYNC();
+        break;
+    }
+  }
+}
+
+// Multi-line variant of line_fft: one thread owns the same element positions of NL
+// lines, so per-element work across the lines (e.g. a 6-component projection) can
+// run in registers between a forward and an inverse transform.  Same LDS contract
+// as line_fft; with OUT_REGS the last stage reads LDS, so a caller that writes LDS
+// next must take a barrier first.
+template <typename T, int E, int NL, bool INV, bool IN_REGS, bool OUT_REGS>
+__device__ __forceinline__ void line_fft_multi(cplx<T> (*v)[E], cplx<T>* lds, const LdsMap& m, int line0,
+                                               int lstride, int p, const FftDesc& d,
+                                               const cplx<T>* __restrict__ tw) {
+  int Ns = 1;
+  for (int s = 0; s < d.nst; ++s) {
+    const int R = d.r[s];
+    const int mode = stage_mode(s, d.nst, IN_REGS, OUT_REGS);
+    switch (R) {
+      case 16: run_stage_multi<T, E, 16, INV, NL>(v, lds, m, line0, lstride, p, d.n, Ns, tw, mode); break;
+      case 8: run_stage_multi<T, E, 8, INV, NL>(v, lds, m, line0, lstride, p, d.n, Ns, tw, mode); break;
+      case 4: run_stage_multi<T, E, 4, INV, NL>(v, lds, m, line0, lstride, p, d.n, Ns, tw, mode); break;
+      case 2: run_stage_multi<T, E, 2, INV, NL>(v, lds, m, line0, lstride, p, d.n, Ns, tw, mode); break;
+      case 3: run_stage_multi<T, E, 3, INV, NL>(v, lds, m, line0, lstride, p, d.n, Ns, tw, mode); break;
+      default: run_stage_multi<T, E, 5, INV, NL>(v, lds, m, line0, lstride, p, d.n, Ns, tw, mode); break;
+    }
+    Ns *= R;
+  }
+}
+
+// Compile-time schedule: radices Rs..., line length N, stages S = 0.. with Ns = product
+// of the radices before S.  The stage helpers see constant n and Ns, so index
+// arithmetic folds and only the live stage code is emitted.
+template <typename T, int E, int NL, bool INV, bool IN_REGS, bool OUT_REGS, int N, int Ns, int S, int NST, int R,
+          int... Rest>
+__device__ __forceinline__ void ct_multi(cplx<T> (*v)[E], cplx<T>* lds, const LdsMap& m, int line0, int lstride,
+                                         int p, const cplx<T>* __restrict__ tw) {
+  static_assert(E % R == 0, "radix must divide E");
+  constexpr bool fr = (S == 0) && IN_REGS;
+  constexpr bool tr = (S == NST - 1) && OUT_REGS;
+  if constexpr (fr && tr) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) stage_a<T, E, R, INV, SM_RR>(v[l], lds, m, line0 + l * lstride, p, N, Ns, tw);
+  } else if constexpr (fr) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) stage_a<T, E, R, INV, SM_RL>(v[l], lds, m, line0 + l * lstride, p, N, Ns, tw);
+    EQ_SYNC();
+  } else if constexpr (tr) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) stage_a<T, E, R, INV, SM_LR>(v[l], lds, m, line0 + l * lstride, p, N, Ns, tw);
+  } else {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) stage_a<T, E, R, INV, SM_LL>(v[l], lds, m, line0 + l * lstride, p, N, Ns, tw);
+    EQ_SYNC();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) stage_b<T, E, R>(v[l], lds, m, line0 + l * lstride, p, N, Ns);
+    EQ_SYNC();
+  }
+  if constexpr (sizeof...(Rest) > 0)
+    ct_multi<T, E, NL, INV, IN_REGS, OUT_REGS, N, Ns * R, S + 1, NST, Rest...>(v, lds, m, line0, lstride, p, tw);
+}
+
+template <int... Rs> struct Sched {
+  static constexpr int n = (Rs * ...);
+  static constexpr int nst = sizeof...(Rs);
+  template <typename T, int E, int NL, bool INV, bool IN_REGS, bool OUT_REGS>
+  static __device__ __forceinline__ void run(cplx<T> (*v)[E], cplx<T>* lds, const LdsMap& m, int line0, int lstride,
+                                             int p, const cplx<T>* __restrict__ tw) {
+    ct_multi<T, E, NL, INV, IN_REGS, OUT_REGS, n, 1, 0, nst, Rs...>(v, lds, m, line0, lstride, p, tw);
+  }
+};
 
 // ------------------------------------------------------- generic engine ---
 

@@ -87,7 +87,8 @@ hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s);
 int pick_tx_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);
 int pick_tx_z(const Geom& g, const AxisFft& az, int elem_bytes, const Tune& tn);
 int pick_rw_x(const Geom& g, const AxisFft& ax, int elem_bytes, const Tune& tn);
-int max_threads(const AxisFft& ax);   // workgroup size limit of the engine that serves this axis
+int max_threads(const AxisFft& ax);
+int x_threads_per_row(const AxisFft& ax, int elem_bytes);   // threads of the x pass per (kz, ky) row   // workgroup size limit of the engine that serves this axis
 size_t lds_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);
 size_t lds_z(const Geom& g, const AxisFft& az, int elem_bytes, const Tune& tn);
 size_t lds_x(const Geom& g, const AxisFft& ax, int elem_bytes, const Tune& tn);

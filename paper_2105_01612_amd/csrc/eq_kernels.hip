@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 
 #include "eq_fft.hpp"
 #include "eq_internal.hpp"
@@ -143,19 +144,18 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_z_r2c_r(const T* __restrict
   for (int i = 0; i < E; ++i) v[i] = *reinterpret_cast<const C*>(src + (size_t)(p + i * P) * plane);
   const LdsMap m{1, np, 0};
   line_fft<T, E, false, true, false>(v, lds, m, line, p, d, tw, true);
-  // separate the two packed columns: A = (Z + conj Zm) / 2, B = (Z - conj Zm) / 2i
-  C* dst = W + (size_t)bc * nzh * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  // separate the two packed columns: A = (Z + conj Zm) / 2, B = (Z - conj Zm) / 2i;
+  // thread (line, p) emits kz = p + i*P for the column pair `line`
+  C* dst = W + (size_t)bc * nzh * plane + (size_t)y * a.nx + (size_t)xt * a.tx + 2 * line;
   const T half = (T)0.5;
-  const int nthr = np * P, total = nzh * np;
   constexpr int NU = E / 2 + 1;
 #pragma unroll
   for (int i = 0; i < NU; ++i) {
-    const int u = threadIdx.x + i * nthr;
-    if (u < total) {
-      const int kz = u / np, j = u - kz * np;
-      const C Z = lds[kz * np + j];
-      const C Zm = lds[((nz - kz) % nz) * np + j];
-      C* o = dst + (size_t)kz * plane + 2 * j;
+    const int kz = p + i * P;
+    if (kz < nzh) {
+      const C Z = lds[kz * np + line];
+      const C Zm = lds[(kz == 0 ? 0 : nz - kz) * np + line];
+      C* o = dst + (size_t)kz * plane;
       o[0] = mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
       o[1] = mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half);
     }
@@ -218,29 +218,28 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_z_c2r_r(const cplx<T>* __re
   const int line = threadIdx.x % np, p = threadIdx.x / np;
   const size_t plane = (size_t)a.ny * a.nx;
   const C* src = W + ((size_t)(b * 6 + c) * nzh) * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
-  const int nthr = np * P, total = nzh * np;
   constexpr int NU = E / 2 + 1;
-  // pack the two columns of each pair into one complex line: Z = A + i B, Z(-k) = conj A + i conj B
+  // pack the two columns of each pair into one complex line: Z = A + i B, Z(-k) = conj A + i conj B;
+  // thread (line, p) reads kz = p + i*P of column pair `line`
+  const C* col = src + 2 * line;
   C ab[NU][2];
 #pragma unroll
   for (int i = 0; i < NU; ++i) {
-    const int u = threadIdx.x + i * nthr;
-    if (u < total) {
-      const int kz = u / np, j = u - kz * np;
-      const C* s = src + (size_t)kz * plane + 2 * j;
+    const int kz = p + i * P;
+    if (kz < nzh) {
+      const C* s = col + (size_t)kz * plane;
       ab[i][0] = s[0];
       ab[i][1] = s[1];
     }
   }
 #pragma unroll
   for (int i = 0; i < NU; ++i) {
-    const int u = threadIdx.x + i * nthr;
-    if (u < total) {
-      const int kz = u / np, j = u - kz * np;
+    const int kz = p + i * P;
+    if (kz < nzh) {
       C A = ab[i][0], B = ab[i][1];
       if (kz == 0 || kz == nyq) { A.y = (T)0; B.y = (T)0; }   // self-conjugate planes are real
-      lds[kz * np + j] = mk<T>(A.x - B.y, A.y + B.x);
-      if (kz > 0 && kz < nyq) lds[(nz - kz) * np + j] = mk<T>(A.x + B.y, B.x - A.y);
+      lds[kz * np + line] = mk<T>(A.x - B.y, A.y + B.x);
+      if (kz > 0 && kz < nyq) lds[(nz - kz) * np + line] = mk<T>(A.x + B.y, B.x - A.y);
     }
   }
   __syncthreads();
@@ -412,24 +411,21 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W
     const double* symx = sym;
     const double* symy = sym + nx;
     const double* symz = sym + nx + a.ny;
-    const int nthr = 6 * rw * P, total = nrows * nx;
-    constexpr int NP = (E + 5) / 6;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const int u = threadIdx.x + i * nthr;
-      if (u < total) {
-        const int rr = u / nx, kx = u - rr * nx;
-        int qz, qy;
-        (void)x_row_base(a, row0 + rr, 0, qz, qy);
+    const int nthr = 6 * rw * P;
+    for (int rr = 0; rr < nrows; ++rr) {
+      int qz, qy;
+      (void)x_row_base(a, row0 + rr, 0, qz, qy);          // uniform across the workgroup
+      const double sy = symy[qy], sz = symz[qz];
+      for (int kx = threadIdx.x; kx < nx; kx += nthr) {
         C A[6];
 #pragma unroll
         for (int cc = 0; cc < 6; ++cc) A[cc] = lds[m.at(cc * rw + rr, kx)];
         if (a.mode & XM_PROJ) {
-          project_one<T>(A, symx[kx], symy[qy], symz[qz]);
+          project_one<T>(A, symx[kx], sy, sz);
 #pragma unroll
           for (int cc = 0; cc < 6; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
         } else {
-          divergence_one<T>(A, symx[kx], symy[qy], symz[qz]);
+          divergence_one<T>(A, symx[kx], sy, sz);
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
         }
@@ -446,6 +442,60 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W
   if (valid && active) {
 #pragma unroll
     for (int i = 0; i < E; ++i) W[base + (size_t)i * P] = v[i];
+  }
+}
+
+// Six-component x pass: thread (row r, p) owns elements p + i*P of all six component
+// rows, so the projection (or divergence) of each of its frequencies runs in registers
+// between the forward and inverse transforms.  LDS holds 6 * rw lines.  The radix
+// schedule SCH is compile-time (E = 8).
+template <typename T, typename SCH>
+__global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ W, XArgs a,
+                                                      const cplx<T>* __restrict__ tw, const double* __restrict__ sym) {
+  using C = cplx<T>;
+  constexpr int E = 8;
+  constexpr int nx = SCH::n, P = nx / E;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int rw = a.rw;
+  const int p = threadIdx.x % P, r = threadIdx.x / P;
+  const int row0 = blockIdx.x * rw;
+  const bool valid = r < min(rw, a.rows - row0);
+  const size_t cstride = (size_t)a.nzh * a.ny * nx;      // between components of one field
+  int kz = 0, ky = 0;
+  const size_t base = valid ? x_row_base(a, row0 + r, 0, kz, ky) + p : 0;
+  C v[6][E];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[c][i] = valid ? W[base + c * cstride + (size_t)i * P] : mk<T>((T)0, (T)0);
+  const LdsMap m{nx + nx / 16 + 1, 1, 1};
+  if (a.mode & XM_FWD) SCH::template run<T, E, 6, false, true, true>(v, lds, m, r, rw, p, tw);
+  if (a.mode & (XM_PROJ | XM_DIV)) {
+    const double sy = sym[nx + ky], sz = sym[nx + a.ny + kz];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int kx = p + i * P;
+      C A[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) A[c] = v[c][i];
+      if (a.mode & XM_PROJ) project_one<T>(A, sym[kx], sy, sz);
+      else divergence_one<T>(A, sym[kx], sy, sz);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c][i] = A[c];
+    }
+  }
+  if (a.mode & XM_INV) {
+    if (a.mode & XM_FWD) __syncthreads();                  // forward's last stage read LDS
+    SCH::template run<T, E, 6, true, true, true>(v, lds, m, r, rw, p, tw);
+  }
+  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (c < ncomp_out)
+#pragma unroll
+        for (int i = 0; i < E; ++i) W[base + c * cstride + (size_t)i * P] = v[c][i];
   }
 }
 
@@ -664,6 +714,19 @@ int largest_pow2_divisor_le(int n, int cap) {
 }  // namespace
 
 // ------------------------------------------------------------- shapes ------
+
+// The six-component x kernel keeps 6 * E complex values per lane: used for E = 8 in
+// FP32 (96 VGPRs of data); EQ_X6=0/1 overrides (FP64 E = 8 doubles that).
+template <typename T>
+bool use_x6(const AxisFft& ax) {
+  // compile-time schedules exist for the powers of two 16 .. 1024 (radix 8 then one 2/4/8)
+  const int n = ax.d.n;
+  if (!ax.fast || ax.E != 8 || n < 16 || (n & (n - 1)) != 0) return false;
+  const char* e = std::getenv("EQ_X6");
+  if (e) return e[0] == '1';
+  return sizeof(T) == 4;
+}
+bool use_x6_eb(const AxisFft& ax, int eb) { return eb == 8 ? use_x6<float>(ax) : use_x6<double>(ax); }
 // Register-engine shapes aim at ~256 threads per workgroup (several workgroups per
 // CU so load, transform and store phases of different workgroups overlap) with
 // tiles at least 128 bytes wide along x.
@@ -704,10 +767,17 @@ int pick_tx_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
 int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
   if (tn.rw_x > 0) return tn.rw_x;
   const int P = g.nx / ax.E;
+  if (use_x6_eb(ax, eb)) {
+    // one thread per (row, p); about 64 threads (one wavefront) per workgroup measured best
+    int rw = 64 / P;
+    if (rw < 1) rw = 1;
+    const int ls = g.nx + g.nx / 16 + 1;
+    while (rw > 1 && (rw * P > kMaxFastThreads || (size_t)6 * rw * ls * eb > kLdsPreferred)) --rw;
+    return rw;
+  }
   if (ax.fast) {
     const int ls = g.nx + g.nx / 16 + 1;
-    int rw = 384 / (6 * P);
-    if (rw < 1) rw = 1;
+    int rw = 1;
     while (rw > 1 && (6 * rw * P > kMaxFastThreads || (size_t)6 * rw * ls * eb > kLdsPreferred)) --rw;
     return rw;
   }
@@ -717,6 +787,7 @@ int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
 }
 
 int max_threads(const AxisFft& ax) { return ax.fast ? kMaxFastThreads : kMaxThreads; }
+int x_threads_per_row(const AxisFft& ax, int eb) { return (use_x6_eb(ax, eb) ? 1 : 6) * (ax.d.n / ax.E); }
 
 size_t lds_y(const Geom& g, const AxisFft& ay, int eb, const Tune& tn) {
   return (size_t)pick_tx_y(g, ay, eb, tn) * g.ny * eb;
@@ -801,7 +872,18 @@ hipError_t launch_x(cplx<T>* W, const Geom& g, int pl0, int npl, int mode, const
   const size_t lds = lds_x(g, ax, eb, tn);
   const dim3 grid((unsigned)((rows + rw - 1) / rw));
   const int P = g.nx / ax.E;
-  if (ax.fast) {
+  if (use_x6<T>(ax)) {
+    const dim3 block(rw * P);
+    switch (g.nx) {
+      case 16: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 2>>), grid, block, lds, s, W, a, tw_x, sym); break;
+      case 32: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 4>>), grid, block, lds, s, W, a, tw_x, sym); break;
+      case 64: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8>>), grid, block, lds, s, W, a, tw_x, sym); break;
+      case 128: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8, 2>>), grid, block, lds, s, W, a, tw_x, sym); break;
+      case 256: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8, 4>>), grid, block, lds, s, W, a, tw_x, sym); break;
+      case 512: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8, 8>>), grid, block, lds, s, W, a, tw_x, sym); break;
+      default: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8, 8, 2>>), grid, block, lds, s, W, a, tw_x, sym); break;
+    }
+  } else if (ax.fast) {
     const dim3 block(6 * rw * P);
     EQ_FAST_E_SWITCH(ax.E, hipLaunchKernelGGL((k_x_r<T, EE>), grid, block, lds, s, W, a, ax.d, tw_x, sym));
   } else {
