@@ -76,7 +76,7 @@ def make_workload(name: str, prec: str):
     return S[None], desc
 
 
-def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True):
+def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tune=True):
     import torch
     import paper_2105_01612_amd as eq
 
@@ -88,6 +88,12 @@ def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True):
         out = torch.empty_like(x)
         rem = torch.empty_like(x)
         norms = None
+        tuned = None
+        if tune:
+            from paper_2105_01612_amd.autotune import autotune
+
+            tuned = autotune(plan, x, out, rem, reps=3, use_cache=False)
+            log(f"[bench] autotuned {prec} {op}: {tuned['tune']} -> {tuned['resolved']}")
         for _ in range(warmup):
             plan.project(x, out, rem)
             if with_residual:
@@ -112,7 +118,8 @@ def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True):
         stats = plan.pass_stats()
         result = out.cpu()
         plan.destroy()
-    return {"elapsed_s": elapsed, "lat_ms": lat, "stats": stats, "out": result, "norms": norms}
+    return {"elapsed_s": elapsed, "lat_ms": lat, "stats": stats, "out": result, "norms": norms,
+            "tune": tuned["resolved"] if tuned else None}
 
 
 def roofline(stats, workload):
@@ -161,12 +168,55 @@ def cpu_baseline(S_field64, op):
                            f"{op.upper()}, numpy + scipy.fft with {cores} workers, {dt:.2f} s"}
 
 
+def run_serve(args):
+    """Poisson stream of requests over six size classes, continuous batching (serve.py)."""
+    import torch
+    from paper_2105_01612_amd import workload as wl
+    from paper_2105_01612_amd.serve import GpuBackend, Request, Server
+
+    sizes = wl.SERVING_SIZES
+    pool_n = {64: 8, 96: 8, 128: 4, 192: 4, 256: 2, 384: 2}
+    t = time.perf_counter()
+    pools = {}
+    for n in sizes:
+        arr = np.stack([wl.voronoi_field(wl.serving_spec(n, j), dtype=np.float32) for j in range(pool_n[n])])
+        pools[n] = torch.from_numpy(arr).cuda()
+        del arr
+    torch.cuda.synchronize()
+    log(f"[bench] serve pools generated in {time.perf_counter() - t:.1f}s: {pool_n}")
+    be = GpuBackend(pools, prec="fp32", op=args.op)
+    srv = Server(be, int(args.budget_gb * 2 ** 30))
+    srv.warm(sizes)
+    ns = wl.request_sizes(args.requests, seed=4000, sizes=sizes)
+    rng = np.random.Generator(np.random.PCG64(4002))
+    fields = [int(rng.integers(0, pool_n[int(n)])) for n in ns]
+    # saturation: every request present at t = 0
+    sat = srv.run([Request(i, int(n), 0.0, f) for i, (n, f) in enumerate(zip(ns, fields))])
+    lam = 0.7 * sat["requests_per_s"]
+    arr = wl.poisson_arrivals(args.requests, lam, seed=4000)
+    res = srv.run([Request(i, int(n), float(a), f) for i, (n, a, f) in enumerate(zip(ns, arr, fields))])
+    over = srv.run([Request(i, int(n), float(a), f) for i, (n, a, f) in
+                    enumerate(zip(ns, wl.poisson_arrivals(args.requests, 1.2 * sat["requests_per_s"], 4001), fields))])
+    srv.close()
+    return {"metric": METRIC, "value": res["voxels_per_s"], "unit": "voxels/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic: serving pools " + str(pool_n),
+            "config": {"workload": f"serve: {args.requests} Poisson requests, N uniform over {list(sizes)}, "
+                                   f"one grain per 16^3 voxels, FP32 {args.op.upper()}, graphs per slot, "
+                                   f"budget {args.budget_gb} GiB"},
+            "arrival_rate_per_s": lam, "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
+            "saturated": sat, "at_0.7_saturation": res, "at_1.2_saturation": over}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="headline", choices=["headline", "small", "largest", "gb_heavy", "batched"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "small", "largest", "gb_heavy", "batched", "serve"])
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for slots")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
     ap.add_argument("--op", default="ddo", choices=["ddo", "cdo"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and CDO side runs")
@@ -189,6 +239,9 @@ def main():
 
     eq.lib()
     log(f"[bench] workload={args.workload} op={args.op} steps={args.steps} warmup={args.warmup}")
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -203,7 +256,8 @@ def main():
     B, _, nz, ny, nx = S32.shape
     vox = B * nz * ny * nx
 
-    r32 = run_gpu(S32, args.op, "fp32", args.steps, args.warmup, timing=not args.no_timing)
+    r32 = run_gpu(S32, args.op, "fp32", args.steps, args.warmup, timing=not args.no_timing,
+                  tune=not args.no_autotune)
     ms32 = r32["elapsed_s"] / args.steps * 1e3
     log(f"[bench] fp32 {args.op}: {ms32:.3f} ms/step")
     roof, per_pass = roofline(r32["stats"], args.workload)
@@ -230,16 +284,17 @@ def main():
         "passes": per_pass,
         "hbm_frac_144B_schedule_min": (vox / r32["elapsed_s"] * args.steps) * 144 / (HBM_PEAK_GBS * 1e9),
         "residual_of_output": r32["norms"][0] if r32["norms"] else None,
+        "tune": r32["tune"],
         "paper_context": PAPER_CONTEXT,
     }
 
     if not args.no_compare and args.workload != "batched":
         S64 = S32.astype(np.float64)
-        r64 = run_gpu(S64, args.op, "fp64", max(3, args.steps // 2), 2, timing=False)
+        r64 = run_gpu(S64, args.op, "fp64", max(3, args.steps // 2), 2, timing=False, tune=not args.no_autotune)
         ms64 = r64["elapsed_s"] / max(3, args.steps // 2) * 1e3
         log(f"[bench] fp64 {args.op}: {ms64:.3f} ms/step")
         other = "cdo" if args.op == "ddo" else "ddo"
-        rc = run_gpu(S32, other, "fp32", max(3, args.steps // 2), 2, timing=False)
+        rc = run_gpu(S32, other, "fp32", max(3, args.steps // 2), 2, timing=False, tune=not args.no_autotune)
         msc = rc["elapsed_s"] / max(3, args.steps // 2) * 1e3
         line["fp64"] = {"value": vox / (ms64 * 1e-3), "ms_per_step": ms64,
                         "p50_ms": statistics.median(r64["lat_ms"]), "p99_ms": float(np.percentile(r64["lat_ms"], 99)),

@@ -128,20 +128,23 @@ eq_status eq_plan_pass_stats(eq_plan_t p, int max, int* count, const char** name
                              long long* launches, double* total_ms, double* bytes_per_launch);
 eq_status eq_plan_reset_stats(eq_plan_t p);
 
-/* Launch-shape tuning (the autotuner's knob; 0 = library default for that knob):
- * tx_y   x-columns per workgroup of the y passes (must divide nx),
- * tx_z   real x-columns per workgroup of the z passes (even, must divide nx),
- * rw_x   (kz, ky) rows per workgroup of the fused x pass,
- * chunk  planes (field, kz) per chunk of the y -> x -> y sequence, so that a
- *        chunk's spectrum can stay in the last-level cache between passes
- *        (0 or -1: one chunk).
- * Invalid shapes for this grid return EQ_ERR_ARG (EQ_ERR_SIZE if LDS would exceed
- * the device limit) and leave the plan unchanged.  Results do not depend on the
- * shapes: every shape computes the same transform with the same arithmetic.
- * The EQ_TUNE environment variable ("tx_y=16,tx_z=32,rw_x=4,chunk=32") seeds the
- * tuning at eq_plan.  eq_plan_get_tune writes the shapes in effect to shape4. */
-eq_status eq_plan_tune(eq_plan_t p, int tx_y, int tx_z, int rw_x, int chunk);
-eq_status eq_plan_get_tune(eq_plan_t p, int* shape4);
+/* Launch-shape and radix-schedule tuning (the autotuner's knobs; 0 = library default for
+ * the shape knobs, -1 for radix16):
+ *   tx_y     x-columns per workgroup of the y passes (must divide nx),
+ *   tx_z     real x-columns per workgroup of the z passes (even, must divide nx),
+ *   rw_x     (kz, ky) rows per workgroup of the fused x pass,
+ *   chunk    planes (field, kz) per chunk of the y -> x -> y sequence, so that a chunk's
+ *            spectrum can stay in the last-level cache between passes (0 or -1: one chunk),
+ *   radix16  bit mask of the axes (1 = x, 2 = y, 4 = z) whose power-of-two edges >= 128 use
+ *            radix-16 stages instead of radix-8 ones; -1 = library default (y only).
+ * Invalid shapes for this grid return EQ_ERR_ARG (EQ_ERR_SIZE if LDS would exceed the device
+ * limit) and leave the plan unchanged.  Every setting computes the same transform; results
+ * may differ only by floating-point rounding order when radix16 changes.
+ * The EQ_TUNE environment variable ("tx_y=16,tx_z=32,rw_x=4,chunk=32,radix16=2") seeds the
+ * tuning at eq_plan.  eq_plan_get_tune reports the settings in effect (defaults resolved). */
+typedef struct { int tx_y, tx_z, rw_x, chunk, radix16; } eq_tune;
+eq_status eq_plan_tune(eq_plan_t p, const eq_tune* t);
+eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t);
 
 /* Test hooks (same kernels as eq_project, exposed for per-stage parity):
  * eq_debug_forward: spec_out (device) = the unnormalized forward DFT of s_in as

@@ -44,6 +44,11 @@ class EqDesc(ctypes.Structure):
                 ("op", ctypes.c_int), ("prec", ctypes.c_int), ("h", ctypes.c_double), ("flags", ctypes.c_uint)]
 
 
+class EqTune(ctypes.Structure):
+    _fields_ = [("tx_y", ctypes.c_int), ("tx_z", ctypes.c_int), ("rw_x", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("radix16", ctypes.c_int)]
+
+
 class EqError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         self.status = status
@@ -80,8 +85,8 @@ def lib() -> ctypes.CDLL:
     L.eq_plan_pass_stats.argtypes = [vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ctypes.c_char_p),
                                      ctypes.POINTER(ctypes.c_longlong), dp, dp]
     L.eq_debug_forward.argtypes = [vp, vp, vp]
-    L.eq_plan_tune.argtypes = [vp, ip, ip, ip, ip]
-    L.eq_plan_get_tune.argtypes = [vp, ctypes.POINTER(ip)]
+    L.eq_plan_tune.argtypes = [vp, ctypes.POINTER(EqTune)]
+    L.eq_plan_get_tune.argtypes = [vp, ctypes.POINTER(EqTune)]
     L.eq_debug_project_spectrum.argtypes = [vp, vp]
     for name in exported_symbols:
         if name not in ("eq_status_str", "eq_last_error", "eq_version"):
@@ -216,14 +221,16 @@ class Plan:
         handle = _stream_handle(stream)
         _check(lib().eq_plan_set_stream(self._h, ctypes.c_void_p(handle) if handle else None), "eq_plan_set_stream")
 
-    def tune(self, tx_y=0, tx_z=0, rw_x=0, chunk=0):
-        """eq_plan_tune: set launch shapes (0 = default); raises EqError if they do not fit."""
-        _check(lib().eq_plan_tune(self._h, int(tx_y), int(tx_z), int(rw_x), int(chunk)), "eq_plan_tune")
+    def tune(self, tx_y=0, tx_z=0, rw_x=0, chunk=0, radix16=-1):
+        """eq_plan_tune: set launch shapes / radix schedule (0 or -1 = default); raises EqError
+        if they do not fit this grid."""
+        t = EqTune(int(tx_y), int(tx_z), int(rw_x), int(chunk), int(radix16))
+        _check(lib().eq_plan_tune(self._h, ctypes.byref(t)), "eq_plan_tune")
 
     def get_tune(self):
-        out = (ctypes.c_int * 4)()
-        _check(lib().eq_plan_get_tune(self._h, out), "eq_plan_get_tune")
-        return {"tx_y": out[0], "tx_z": out[1], "rw_x": out[2], "chunk": out[3]}
+        t = EqTune()
+        _check(lib().eq_plan_get_tune(self._h, ctypes.byref(t)), "eq_plan_get_tune")
+        return {"tx_y": t.tx_y, "tx_z": t.tx_z, "rw_x": t.rw_x, "chunk": t.chunk, "radix16": t.radix16}
 
     def set_timing(self, enable: bool):
         _check(lib().eq_plan_set_timing(self._h, 1 if enable else 0), "eq_plan_set_timing")

@@ -331,10 +331,19 @@ Tune tune_from_env() {
       else if (key == "tx_z") t.tx_z = val;
       else if (key == "rw_x") t.rw_x = val;
       else if (key == "chunk") t.chunk = val;
+      else if (key == "radix16") t.radix16 = val;
     }
     pos = end + 1;
   }
   return t;
+}
+
+// Radix schedules of the three axes for a radix-16 mask (-1: y only).
+void set_axes(eq_plan_s* p, int mask) {
+  if (mask < 0) mask = 2;
+  factor_axis(p->desc.nx, &p->ax, (mask & 1) != 0);
+  factor_axis(p->desc.ny, &p->ay, (mask & 2) != 0);
+  factor_axis(p->desc.nz, &p->az, (mask & 4) != 0);
 }
 
 // Planes per chunk of the y/x/y sequence (the whole range when chunking is off).
@@ -527,13 +536,11 @@ eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out) {
   eq_plan_s* p = new (std::nothrow) eq_plan_s();
   if (!p) return fail(EQ_ERR_NOMEM, "host allocation failed");
   p->desc = *d;
-  factor_axis(d->nx, &p->ax, false);
-  factor_axis(d->ny, &p->ay, true);
-  factor_axis(d->nz, &p->az, false);
   p->g = Geom{d->nx, d->ny, d->nz, d->nz / 2 + 1, d->batch};
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }
   p->tune = tune_from_env();
+  set_axes(p, p->tune.radix16);
   if ((st = check_shapes(p, p->tune)) != EQ_OK) { release(p); return st; }
   if (d->flags & EQ_F_OWN_STREAM) {
     e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
@@ -633,27 +640,35 @@ eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_
                                  : run_residual<float>(p, s, norms_host, div_out);
 }
 
-eq_status eq_plan_tune(eq_plan_t p, int tx_y, int tx_z, int rw_x, int chunk) {
-  if (!p) return fail(EQ_ERR_ARG, "null plan");
+eq_status eq_plan_tune(eq_plan_t p, const eq_tune* tv) {
+  if (!p || !tv) return fail(EQ_ERR_ARG, "null pointer");
+  if (tv->tx_y < 0 || tv->tx_z < 0 || tv->rw_x < 0) return fail(EQ_ERR_ARG, "negative launch shape");
+  if (tv->radix16 < -1 || tv->radix16 > 7) return fail(EQ_ERR_ARG, "radix16 must be -1 or a mask of 1|2|4");
   Tune t;
-  t.tx_y = tx_y; t.tx_z = tx_z; t.rw_x = rw_x; t.chunk = chunk;
-  if (tx_y < 0 || tx_z < 0 || rw_x < 0) return fail(EQ_ERR_ARG, "negative launch shape");
+  t.tx_y = tv->tx_y; t.tx_z = tv->tx_z; t.rw_x = tv->rw_x; t.chunk = tv->chunk;
+  t.radix16 = tv->radix16;
   DeviceGuard dg(p->device);
+  const AxisFft ax = p->ax, ay = p->ay, az = p->az;
+  set_axes(p, t.radix16);
   eq_status st = check_shapes(p, t);
-  if (st != EQ_OK) return st;
+  if (st != EQ_OK) {
+    p->ax = ax; p->ay = ay; p->az = az;
+    return st;
+  }
   EQ_HIP(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
   drop_graphs(p);
   p->tune = t;
   return EQ_OK;
 }
 
-eq_status eq_plan_get_tune(eq_plan_t p, int* shape4) {
-  if (!p || !shape4) return fail(EQ_ERR_ARG, "null pointer");
+eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t) {
+  if (!p || !t) return fail(EQ_ERR_ARG, "null pointer");
   const int eb = 2 * (int)elem_size(&p->desc);
-  shape4[0] = pick_tx_y(p->g, p->ay, eb, p->tune);
-  shape4[1] = pick_tx_z(p->g, p->az, eb, p->tune);
-  shape4[2] = pick_rw_x(p->g, p->ax, eb, p->tune);
-  shape4[3] = chunk_planes(p);
+  t->tx_y = pick_tx_y(p->g, p->ay, eb, p->tune);
+  t->tx_z = pick_tx_z(p->g, p->az, eb, p->tune);
+  t->rw_x = pick_rw_x(p->g, p->ax, eb, p->tune);
+  t->chunk = chunk_planes(p);
+  t->radix16 = (p->ax.E == 16 ? 1 : 0) | (p->ay.E == 16 ? 2 : 0) | (p->az.E == 16 ? 4 : 0);
   return EQ_OK;
 }
 

@@ -29,6 +29,7 @@ struct Tune {
   int tx_z = 0;    // x-tile width of the z passes (real columns per workgroup, even)
   int rw_x = 0;    // rows per workgroup of the fused x pass
   int chunk = 0;   // planes per chunk of the y/x/y sequence (0 = library default, -1 = no chunking)
+  int radix16 = -1;  // axes (1 = x, 2 = y, 4 = z) using radix-16 schedules; -1 = default (y)
 };
 
 // Modes of the fused x pass.

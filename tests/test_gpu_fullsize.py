@@ -1,0 +1,138 @@
+"""GPU parity at the benchmark sizes: 160^3 against the whole-field oracle, 512^3 on
+sampled frequencies (the oracle's per-frequency projection of the input's DFT at q
+against the DFT of the GPU output at q) plus invariants that hold at any size, and
+the 64 x 128^3 batch field by field.
+
+Sizes and distributions are those of the benchmark workloads (see workload.py)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2105_01612_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+W6 = np.array([1.0, 1.0, 1.0, 2.0, 2.0, 2.0])
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def frob_rel(got, ref):
+    w = W6.reshape((6,) + (1,) * (ref.ndim - 1))
+    d = got.astype(np.float64) - ref
+    return math.sqrt(float(np.sum(w * d * d)) / float(np.sum(w * ref * ref)))
+
+
+def dft_at(F, qs):
+    """DFT of each component of F (6, nz, ny, nx) at integer frequencies qs [(qx, qy, qz)]:
+    sum_x F(x) exp(-2 pi i q.x / N), evaluated as separable contractions."""
+    _, nz, ny, nx = F.shape
+    qs = np.asarray(qs)
+    ex = np.exp(-2j * math.pi * np.outer(np.arange(nx), qs[:, 0]) / nx)      # (nx, nq)
+    ey = np.exp(-2j * math.pi * np.outer(np.arange(ny), qs[:, 1]) / ny)
+    ez = np.exp(-2j * math.pi * np.outer(np.arange(nz), qs[:, 2]) / nz)
+    out = np.empty((6, len(qs)), dtype=np.complex128)
+    for c in range(6):
+        t = F[c].astype(np.float64).reshape(nz * ny, nx) @ ex                    # (nz*ny, nq)
+        t = t.reshape(nz, ny, len(qs))
+        t = np.einsum("zyq,yq->zq", t, ey)
+        out[c] = np.einsum("zq,zq->q", t, ez)
+    return out
+
+
+def sampled_parity(S_in64, S_out, op, h, qs):
+    """Per sampled q: |DFT(out)(q) - P A(q) P| / ||S||_2 with A(q) = DFT(in)(q).  By Parseval the
+    root-mean-square of this over all q is the whole-field rel-L2, so the RMS over the samples
+    estimates it; low-order coefficients (coherent sums) carry larger absolute FP32 error."""
+    nz, ny, nx = S_in64.shape[1:]
+    A = dft_at(S_in64, qs)
+    B = dft_at(S_out, qs)
+    sx, sy, sz = O.axis_symbol(op, nx, h), O.axis_symbol(op, ny, h), O.axis_symbol(op, nz, h)
+    s = np.stack([np.array([sx[q[0]], sy[q[1]], sz[q[2]]]) for q in qs], axis=1)   # (3, nq)
+    ref = O.matrix_to_voigt(O.project_spectrum_pap(O.voigt_to_matrix(A), s))
+    scale = math.sqrt(float(np.mean(S_in64.astype(np.float64) ** 2)) * S_in64[0].size)
+    return np.abs(B - ref).max(axis=0) / scale
+
+
+def run(S, op, prec, h=1.0, batch=None):
+    import torch
+    import paper_2105_01612_amd as eq
+
+    nz, ny, nx = S.shape[-3:]
+    b = S.shape[0] if S.ndim == 5 else 1
+    plan = eq.plan(nx, ny, nz, batch=b, op=op, prec=prec, h=h)
+    x = torch.from_numpy(np.ascontiguousarray(S)).cuda()
+    out = torch.empty_like(x)
+    rem = torch.empty_like(x)
+    plan.project(x, out, rem)
+    norms = plan.residual(out)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy(), rem.cpu().numpy(), norms
+    plan.destroy()
+    del x, out, rem
+    torch.cuda.empty_cache()
+    return res
+
+
+@pytest.mark.parametrize("op", ["ddo", "cdo"])
+def test_gb_heavy_160_fp32_whole_field(op):
+    say("gb_heavy 160^3", op)
+    S = wl.config_field("gb_heavy", dtype=np.float32)
+    got, rem, norms = run(S, op, "fp32")
+    ref, ref_rem = O.project(S.astype(np.float64), op)
+    err = frob_rel(got, ref)
+    say("  rel-L2", err, "max-abs", float(np.abs(got - ref).max()), "residual rel", norms[0][2])
+    assert err <= 1e-5
+    assert norms[0][2] <= 2e-6
+
+
+def test_largest_512_fp32_whole_field_sampled_and_invariants():
+    say("largest 512^3: generating")
+    S = wl.config_field("largest", dtype=np.float32)
+    say("  projecting")
+    got, rem, norms = run(S, "ddo", "fp32")
+    S64 = S.astype(np.float64)
+    rng = np.random.default_rng(512)
+    qs = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (256, 0, 0), (256, 256, 256), (3, 5, 7), (255, 1, 2),
+          (100, 300, 511)] + [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(7)]
+    errs = sampled_parity(S64, got, "ddo", 1.0, qs)
+    say("  sampled spectral errors", dict(zip(map(str, qs), np.round(errs, 9))), "rms", float(np.sqrt(np.mean(errs ** 2))))
+    assert float(np.sqrt(np.mean(errs ** 2))) <= 1e-5
+    # invariants at full size: divergence-free (the library's residual), mean kept, removed = in - out,
+    # Frobenius orthogonality of removed part and demeaned result
+    assert norms[0][2] <= 2e-6
+    assert np.abs(got.mean(axis=(1, 2, 3), dtype=np.float64) - S64.mean(axis=(1, 2, 3))).max() <= 1e-5 * np.abs(S).max()
+    assert np.abs(rem.astype(np.float64) + got - S64).max() <= 1e-4 * np.abs(S).max()
+    dev = got.astype(np.float64) - got.mean(axis=(1, 2, 3), dtype=np.float64)[:, None, None, None]
+    dot = O.frobenius_dot(rem.astype(np.float64), dev)
+    assert abs(dot) <= 1e-5 * O.frobenius_norm(rem.astype(np.float64)) * O.frobenius_norm(dev)
+    del rem, dev
+    say("  whole-field oracle")
+    ref, _ = O.project(S64, "ddo")
+    err = frob_rel(got, ref)
+    say("  whole-field rel-L2", err, "max-abs MPa", float(np.abs(got - ref).max()))
+    assert err <= 1e-5
+
+
+def test_batched_64x128_fp32_per_field():
+    import torch
+    import paper_2105_01612_amd as eq
+
+    say("batched 64 x 128^3: generating")
+    specs = wl.batched_specs()
+    S = np.stack([wl.voronoi_field(sp, dtype=np.float32) for sp in specs])
+    say("  projecting")
+    got, rem, norms = run(S, "ddo", "fp32")
+    assert len(norms) == 64 and max(n[2] for n in norms) <= 2e-6
+    for b in (0, 17, 63):
+        ref, _ = O.project(S[b].astype(np.float64), "ddo")
+        err = frob_rel(got[b], ref)
+        say("  field", b, "rel-L2", err)
+        assert err <= 1e-5
+    # a field inside the batch equals the same field alone, bitwise
+    single, _, _ = run(S[17], "ddo", "fp32")
+    assert np.array_equal(single, got[17])
