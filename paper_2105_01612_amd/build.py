@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libeq.so")
-SOURCES = ["eq_kernels.hip", "eq_capi.cpp"]
+SOURCES = ["eq_kernels.hip", "eq_sched_pow2_f32.hip", "eq_sched_pow2_f64.hip", "eq_sched_mixed.hip", "eq_capi.cpp"]
 ARCH = os.environ.get("EQ_OFFLOAD_ARCH", "gfx950")
 
 

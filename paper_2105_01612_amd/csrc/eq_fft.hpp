@@ -389,13 +389,37 @@ __device__ __forceinline__ void ct_multi(cplx<T> (*v)[E], cplx<T>* lds, const Ld
     ct_multi<T, E, NL, INV, IN_REGS, OUT_REGS, N, Ns * R, S + 1, NST, Rest...>(v, lds, m, line0, lstride, p, tw);
 }
 
+constexpr int gcd_ct(int a, int b) { return b == 0 ? a : gcd_ct(b, a % b); }
+constexpr int lcm_ct(int a, int b) { return a / gcd_ct(a, b) * b; }
+template <int... Rs> struct LcmOf;
+template <int R> struct LcmOf<R> { static constexpr int value = R; };
+template <int R, int... Rest> struct LcmOf<R, Rest...> {
+  static constexpr int value = lcm_ct(R, LcmOf<Rest...>::value);
+};
+
+// FFT policies used by the kernels.  Both expose E (elements per thread), len(d) (the
+// line length: a constant for a compile-time schedule) and run<T, NL, INV, IN, OUT>().
+// Sched<R...>: compile-time radix schedule (index arithmetic folds, only live stage
+// code is emitted); RtFft<E>: radices read from the FftDesc at run time.
 template <int... Rs> struct Sched {
-  static constexpr int n = (Rs * ...);
+  static constexpr int N = (Rs * ...);
   static constexpr int nst = sizeof...(Rs);
-  template <typename T, int E, int NL, bool INV, bool IN_REGS, bool OUT_REGS>
+  static constexpr int E = LcmOf<Rs...>::value;
+  static EQ_HD constexpr int len(const FftDesc&) { return N; }
+  template <typename T, int NL, bool INV, bool IN_REGS, bool OUT_REGS>
   static __device__ __forceinline__ void run(cplx<T> (*v)[E], cplx<T>* lds, const LdsMap& m, int line0, int lstride,
-                                             int p, const cplx<T>* __restrict__ tw) {
-    ct_multi<T, E, NL, INV, IN_REGS, OUT_REGS, n, 1, 0, nst, Rs...>(v, lds, m, line0, lstride, p, tw);
+                                             int p, const FftDesc&, const cplx<T>* __restrict__ tw) {
+    ct_multi<T, E, NL, INV, IN_REGS, OUT_REGS, N, 1, 0, nst, Rs...>(v, lds, m, line0, lstride, p, tw);
+  }
+};
+
+template <int E_> struct RtFft {
+  static constexpr int E = E_;
+  static EQ_HD int len(const FftDesc& d) { return d.n; }
+  template <typename T, int NL, bool INV, bool IN_REGS, bool OUT_REGS>
+  static __device__ __forceinline__ void run(cplx<T> (*v)[E], cplx<T>* lds, const LdsMap& m, int line0, int lstride,
+                                             int p, const FftDesc& d, const cplx<T>* __restrict__ tw) {
+    line_fft_multi<T, E, NL, INV, IN_REGS, OUT_REGS>(v, lds, m, line0, lstride, p, d, tw);
   }
 };
 

@@ -13,11 +13,13 @@
 // over contiguous x with lanes running along x, so every global access is a
 // contiguous run of tile-width elements; the x pass reads whole rows.
 //
-// Register-engine kernels (suffix _r): each thread issues all E global loads of
-// its line segment back to back, runs the first FFT stage on them in registers,
-// exchanges through LDS between stages, and stores the last stage's registers
-// directly.  Generic kernels (suffix _g) stage whole tiles through LDS; they
-// serve edges the register engine does not schedule.
+// Register-engine kernels (eq_kernels_impl.hpp) issue all E global loads of a
+// thread's line segment back to back, run the first FFT stage on them in
+// registers, exchange through LDS between stages, and store the last stage's
+// registers directly; their radix schedule is compile-time for the common edges
+// (eq_sched_*.hip) and read at run time otherwise.  Generic kernels (suffix _g,
+// this file) stage whole tiles through LDS; they serve edges the register engine
+// does not schedule.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,14 +28,11 @@
 
 #include "eq_fft.hpp"
 #include "eq_internal.hpp"
+#include "eq_kernels_impl.hpp"
 
 namespace eq {
 
 namespace {
-
-constexpr int kMaxThreads = 1024;      // generic-engine workgroups
-constexpr int kMaxFastThreads = 512;   // register-engine workgroups (up to 256 VGPRs per lane)
-constexpr size_t kLdsPreferred = 64 * 1024;
 
 // ------------------------------------------------------------- tables ------
 
@@ -62,105 +61,7 @@ __global__ void k_tables(int nx, int ny, int nz, int op, double h, double* __res
   }
 }
 
-// ----------------------------------------------------- per-frequency ops ---
-
-// Projection of one frequency: out = P A P, P = I - n n^T, n = s / |s| formed in FP64.
-// Voigt slots: 0=11 1=22 2=33 3=23 4=13 5=12.
-template <typename T>
-__device__ __forceinline__ void project_one(cplx<T>* A /*6*/, double sx, double sy, double sz) {
-  using C = cplx<T>;
-  const double ss = sx * sx + sy * sy + sz * sz;
-  if (!(ss > 0.0)) return;                                   // zero symbol: divergence-free, kept
-  const double inv = 1.0 / sqrt(ss);
-  const T n0 = (T)(sx * inv), n1 = (T)(sy * inv), n2 = (T)(sz * inv);
-  const C a00 = A[0], a11 = A[1], a22 = A[2], a12 = A[3], a02 = A[4], a01 = A[5];
-  // b = A n
-  C b0, b1, b2;
-  b0.x = a00.x * n0 + a01.x * n1 + a02.x * n2;  b0.y = a00.y * n0 + a01.y * n1 + a02.y * n2;
-  b1.x = a01.x * n0 + a11.x * n1 + a12.x * n2;  b1.y = a01.y * n0 + a11.y * n1 + a12.y * n2;
-  b2.x = a02.x * n0 + a12.x * n1 + a22.x * n2;  b2.y = a02.y * n0 + a12.y * n1 + a22.y * n2;
-  // c = n . b
-  C cc;
-  cc.x = n0 * b0.x + n1 * b1.x + n2 * b2.x;
-  cc.y = n0 * b0.y + n1 * b1.y + n2 * b2.y;
-  // out_ij = A_ij - n_i b_j - b_i n_j + c n_i n_j
-  auto upd = [&](C aij, T ni, T nj, C bi, C bj) -> C {
-    C o;
-    const T nn = ni * nj;
-    o.x = aij.x - ni * bj.x - nj * bi.x + cc.x * nn;
-    o.y = aij.y - ni * bj.y - nj * bi.y + cc.y * nn;
-    return o;
-  };
-  A[0] = upd(a00, n0, n0, b0, b0);
-  A[1] = upd(a11, n1, n1, b1, b1);
-  A[2] = upd(a22, n2, n2, b2, b2);
-  A[3] = upd(a12, n1, n2, b1, b2);
-  A[4] = upd(a02, n0, n2, b0, b2);
-  A[5] = upd(a01, n0, n1, b0, b1);
-}
-
-// Divergence of one frequency: r_i = sum_j (i s_j) A_ij, written to slots 0..2.
-template <typename T>
-__device__ __forceinline__ void divergence_one(cplx<T>* A, double sx, double sy, double sz) {
-  using C = cplx<T>;
-  const T s0 = (T)sx, s1 = (T)sy, s2 = (T)sz;
-  const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
-  C r3[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const C p = A[idx[i][0]], q = A[idx[i][1]], w = A[idx[i][2]];
-    const T re = s0 * p.x + s1 * q.x + s2 * w.x;
-    const T im = s0 * p.y + s1 * q.y + s2 * w.y;
-    r3[i] = mk<T>(-im, re);
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) A[i] = r3[i];
-}
-
-// ------------------------------------------------------------- z passes ----
-
-struct ZArgs {
-  int nx, ny, nz, tx;      // tx: real x-columns per workgroup (even)
-};
-
-template <typename T, int E>
-__global__ __launch_bounds__(kMaxFastThreads) void k_z_r2c_r(const T* __restrict__ in, cplx<T>* __restrict__ W, ZArgs a,
-                                                         FftDesc d, const cplx<T>* __restrict__ tw) {
-  using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int ntx = a.nx / a.tx;
-  int bid = blockIdx.x;
-  const int xt = bid % ntx; bid /= ntx;
-  const int y = bid % a.ny;
-  const int bc = bid / a.ny;                        // b * 6 + c
-  const int np = a.tx >> 1;                         // complex lines (column pairs)
-  const int nz = a.nz, nzh = nz / 2 + 1, P = nz / E;
-  const int line = threadIdx.x % np, p = threadIdx.x / np;
-  const size_t plane = (size_t)a.ny * a.nx;
-  const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx + 2 * line;
-  C v[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = *reinterpret_cast<const C*>(src + (size_t)(p + i * P) * plane);
-  const LdsMap m{1, np, 0};
-  line_fft<T, E, false, true, false>(v, lds, m, line, p, d, tw, true);
-  // separate the two packed columns: A = (Z + conj Zm) / 2, B = (Z - conj Zm) / 2i;
-  // thread (line, p) emits kz = p + i*P for the column pair `line`
-  C* dst = W + (size_t)bc * nzh * plane + (size_t)y * a.nx + (size_t)xt * a.tx + 2 * line;
-  const T half = (T)0.5;
-  constexpr int NU = E / 2 + 1;
-#pragma unroll
-  for (int i = 0; i < NU; ++i) {
-    const int kz = p + i * P;
-    if (kz < nzh) {
-      const C Z = lds[kz * np + line];
-      const C Zm = lds[(kz == 0 ? 0 : nz - kz) * np + line];
-      C* o = dst + (size_t)kz * plane;
-      o[0] = mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
-      o[1] = mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half);
-    }
-  }
-}
+// ------------------------------------------------------- generic kernels ---
 
 template <typename T, int E>
 __global__ __launch_bounds__(kMaxThreads) void k_z_r2c_g(const T* __restrict__ in, cplx<T>* __restrict__ W, ZArgs a,
@@ -192,77 +93,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_z_r2c_g(const T* __restrict__ i
     C* o = dst + (size_t)kz * plane + 2 * j;
     o[0] = mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
     o[1] = mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half);
-  }
-}
-
-struct ZcArgs {
-  int nx, ny, nz, tx, ncomp;
-  size_t out_field, out_comp;
-};
-
-template <typename T, int E>
-__global__ __launch_bounds__(kMaxFastThreads) void k_z_c2r_r(const cplx<T>* __restrict__ W, T* out, const T* in,
-                                                         T* removed, ZcArgs a, FftDesc d,
-                                                         const cplx<T>* __restrict__ tw, T scale) {
-  using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int ntx = a.nx / a.tx;
-  int bid = blockIdx.x;
-  const int xt = bid % ntx; bid /= ntx;
-  const int y = bid % a.ny; bid /= a.ny;
-  const int c = bid % a.ncomp;
-  const int b = bid / a.ncomp;
-  const int np = a.tx >> 1;
-  const int nz = a.nz, nzh = nz / 2 + 1, nyq = nz / 2, P = nz / E;
-  const int line = threadIdx.x % np, p = threadIdx.x / np;
-  const size_t plane = (size_t)a.ny * a.nx;
-  const C* src = W + ((size_t)(b * 6 + c) * nzh) * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
-  constexpr int NU = E / 2 + 1;
-  // pack the two columns of each pair into one complex line: Z = A + i B, Z(-k) = conj A + i conj B;
-  // thread (line, p) reads kz = p + i*P of column pair `line`
-  const C* col = src + 2 * line;
-  C ab[NU][2];
-#pragma unroll
-  for (int i = 0; i < NU; ++i) {
-    const int kz = p + i * P;
-    if (kz < nzh) {
-      const C* s = col + (size_t)kz * plane;
-      ab[i][0] = s[0];
-      ab[i][1] = s[1];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < NU; ++i) {
-    const int kz = p + i * P;
-    if (kz < nzh) {
-      C A = ab[i][0], B = ab[i][1];
-      if (kz == 0 || kz == nyq) { A.y = (T)0; B.y = (T)0; }   // self-conjugate planes are real
-      lds[kz * np + line] = mk<T>(A.x - B.y, A.y + B.x);
-      if (kz > 0 && kz < nyq) lds[(nz - kz) * np + line] = mk<T>(A.x + B.y, B.x - A.y);
-    }
-  }
-  __syncthreads();
-  C v[E];
-  const LdsMap m{1, np, 0};
-  line_fft<T, E, true, false, true>(v, lds, m, line, p, d, tw, true);
-  const size_t obase = (size_t)b * a.out_field + (size_t)c * a.out_comp + (size_t)y * a.nx + (size_t)xt * a.tx +
-                       2 * line;
-  if (removed) {
-    C s[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) s[i] = *reinterpret_cast<const C*>(in + obase + (size_t)(p + i * P) * plane);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const C o = mk<T>(v[i].x * scale, v[i].y * scale);
-      const size_t off = obase + (size_t)(p + i * P) * plane;
-      *reinterpret_cast<C*>(removed + off) = mk<T>(s[i].x - o.x, s[i].y - o.y);
-      *reinterpret_cast<C*>(out + off) = o;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < E; ++i)
-      *reinterpret_cast<C*>(out + obase + (size_t)(p + i * P) * plane) = mk<T>(v[i].x * scale, v[i].y * scale);
   }
 }
 
@@ -307,52 +137,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_z_c2r_g(const cplx<T>* __restri
   }
 }
 
-// ------------------------------------------------------------- y pass ------
-
-struct YArgs {
-  int nx, ny, nzh, ncomp, tx, pl0, npl;
-};
-
-__device__ __forceinline__ size_t y_tile_base(const YArgs& a, int& xt_out) {
-  const int ntx = a.nx / a.tx;
-  int bid = blockIdx.x;
-  const int xt = bid % ntx; bid /= ntx;
-  const int pll = bid % a.npl;
-  const int c = bid / a.npl;
-  const int pl = a.pl0 + pll;
-  const int b = pl / a.nzh, kz = pl - b * a.nzh;
-  xt_out = xt;
-  return (((size_t)(b * 6 + c) * a.nzh + kz) * a.ny) * a.nx + (size_t)xt * a.tx;
-}
-
-template <typename T, int E, bool INV>
-__global__ __launch_bounds__(kMaxFastThreads) void k_y_r(cplx<T>* __restrict__ W, YArgs a, FftDesc d,
-                                                     const cplx<T>* __restrict__ tw) {
-  using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  int xt;
-  C* base = W + y_tile_base(a, xt);
-  const int tx = a.tx, P = a.ny / E;
-  const int line = threadIdx.x % tx, p = threadIdx.x / tx;
-  C* col = base + line;
-  C v[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = col[(size_t)(p + i * P) * a.nx];
-  const LdsMap m{1, tx, 0};
-  line_fft<T, E, INV, true, true>(v, lds, m, line, p, d, tw, true);
-#pragma unroll
-  for (int i = 0; i < E; ++i) col[(size_t)(p + i * P) * a.nx] = v[i];
-}
-
 template <typename T, int E, bool INV>
 __global__ __launch_bounds__(kMaxThreads) void k_y_g(cplx<T>* __restrict__ W, YArgs a, FftDesc d,
                                                      const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
-  int xt;
-  C* base = W + y_tile_base(a, xt);
+  C* base = W + y_tile_base(a);
   const int tx = a.tx;
   for (int u = threadIdx.x; u < a.ny * tx; u += blockDim.x) {
     const int y = u / tx, x = u - y * tx;
@@ -363,139 +154,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_y_g(cplx<T>* __restrict__ W, YA
   for (int u = threadIdx.x; u < a.ny * tx; u += blockDim.x) {
     const int y = u / tx, x = u - y * tx;
     base[(size_t)y * a.nx + x] = lds[u];
-  }
-}
-
-// ------------------------------------------------------------- x pass ------
-
-struct XArgs {
-  int nx, ny, nzh, pl0, rows, rw, mode;   // rows = planes in range * ny
-};
-
-__device__ __forceinline__ size_t x_row_base(const XArgs& a, int row, int c, int& kz, int& ky) {
-  const int pl = a.pl0 + row / a.ny;
-  ky = row - (row / a.ny) * a.ny;
-  const int b = pl / a.nzh;
-  kz = pl - b * a.nzh;
-  return (((size_t)(b * 6 + c) * a.nzh + kz) * a.ny + ky) * a.nx;
-}
-
-template <typename T, int E>
-__global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
-                                                     const cplx<T>* __restrict__ tw, const double* __restrict__ sym) {
-  using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int nx = a.nx, rw = a.rw, P = nx / E;
-  const int p = threadIdx.x % P, line = threadIdx.x / P;   // line = c * rw + r
-  const int c = line / rw, r = line - c * rw;
-  const int row0 = blockIdx.x * rw;
-  const int nrows = min(rw, a.rows - row0);
-  const bool valid = r < nrows;
-  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
-  const bool active = c < ncomp_out;
-  int kz, ky;
-  const size_t base = valid ? x_row_base(a, row0 + r, c, kz, ky) + p : 0;
-  C v[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = valid ? W[base + (size_t)i * P] : mk<T>((T)0, (T)0);
-  const LdsMap m{nx + nx / 16 + 1, 1, 1};
-  if (a.mode & XM_FWD) {
-    line_fft<T, E, false, true, false>(v, lds, m, line, p, d, tw, true);
-  } else {
-#pragma unroll
-    for (int i = 0; i < E; ++i) lds[m.at(line, p + i * P)] = v[i];
-    __syncthreads();
-  }
-  if (a.mode & (XM_PROJ | XM_DIV)) {
-    const double* symx = sym;
-    const double* symy = sym + nx;
-    const double* symz = sym + nx + a.ny;
-    const int nthr = 6 * rw * P;
-    for (int rr = 0; rr < nrows; ++rr) {
-      int qz, qy;
-      (void)x_row_base(a, row0 + rr, 0, qz, qy);          // uniform across the workgroup
-      const double sy = symy[qy], sz = symz[qz];
-      for (int kx = threadIdx.x; kx < nx; kx += nthr) {
-        C A[6];
-#pragma unroll
-        for (int cc = 0; cc < 6; ++cc) A[cc] = lds[m.at(cc * rw + rr, kx)];
-        if (a.mode & XM_PROJ) {
-          project_one<T>(A, symx[kx], sy, sz);
-#pragma unroll
-          for (int cc = 0; cc < 6; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
-        } else {
-          divergence_one<T>(A, symx[kx], sy, sz);
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (a.mode & XM_INV) {
-    line_fft<T, E, true, false, true>(v, lds, m, line, p, d, tw, active);
-  } else {
-#pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = lds[m.at(line, p + i * P)];
-  }
-  if (valid && active) {
-#pragma unroll
-    for (int i = 0; i < E; ++i) W[base + (size_t)i * P] = v[i];
-  }
-}
-
-// Six-component x pass: thread (row r, p) owns elements p + i*P of all six component
-// rows, so the projection (or divergence) of each of its frequencies runs in registers
-// between the forward and inverse transforms.  LDS holds 6 * rw lines.  The radix
-// schedule SCH is compile-time (E = 8).
-template <typename T, typename SCH>
-__global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ W, XArgs a,
-                                                      const cplx<T>* __restrict__ tw, const double* __restrict__ sym) {
-  using C = cplx<T>;
-  constexpr int E = 8;
-  constexpr int nx = SCH::n, P = nx / E;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int rw = a.rw;
-  const int p = threadIdx.x % P, r = threadIdx.x / P;
-  const int row0 = blockIdx.x * rw;
-  const bool valid = r < min(rw, a.rows - row0);
-  const size_t cstride = (size_t)a.nzh * a.ny * nx;      // between components of one field
-  int kz = 0, ky = 0;
-  const size_t base = valid ? x_row_base(a, row0 + r, 0, kz, ky) + p : 0;
-  C v[6][E];
-#pragma unroll
-  for (int c = 0; c < 6; ++c)
-#pragma unroll
-    for (int i = 0; i < E; ++i) v[c][i] = valid ? W[base + c * cstride + (size_t)i * P] : mk<T>((T)0, (T)0);
-  const LdsMap m{nx + nx / 16 + 1, 1, 1};
-  if (a.mode & XM_FWD) SCH::template run<T, E, 6, false, true, true>(v, lds, m, r, rw, p, tw);
-  if (a.mode & (XM_PROJ | XM_DIV)) {
-    const double sy = sym[nx + ky], sz = sym[nx + a.ny + kz];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int kx = p + i * P;
-      C A[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) A[c] = v[c][i];
-      if (a.mode & XM_PROJ) project_one<T>(A, sym[kx], sy, sz);
-      else divergence_one<T>(A, sym[kx], sy, sz);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[c][i] = A[c];
-    }
-  }
-  if (a.mode & XM_INV) {
-    if (a.mode & XM_FWD) __syncthreads();                  // forward's last stage read LDS
-    SCH::template run<T, E, 6, true, true, true>(v, lds, m, r, rw, p, tw);
-  }
-  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
-  if (valid) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      if (c < ncomp_out)
-#pragma unroll
-        for (int i = 0; i < E; ++i) W[base + c * cstride + (size_t)i * P] = v[c][i];
   }
 }
 
@@ -703,6 +361,25 @@ __global__ void k_fill_int(int* p, int n, int value) {
 template <typename T>
 size_t csize() { return sizeof(cplx<T>); }
 
+// Compile-time radix schedules on (default) or off (EQ_CT=0, for comparisons).
+bool ct_enabled() {
+  const char* e = std::getenv("EQ_CT");
+  return !(e && e[0] == '0');
+}
+
+// Issue a register-engine launch: a compile-time schedule when one matches the
+// axis's radix list, else the run-time schedule.
+template <typename T>
+void dispatch_fast(const FastArgs<T>& a) {
+  if (ct_enabled() && (ct_launch_pow2<T>(a) || ct_launch_mixed<T>(a))) return;
+  switch (a.E) {
+    case 8: launch_with<T, RtFft<8>>(a); break;
+    case 16: launch_with<T, RtFft<16>>(a); break;
+    case 24: launch_with<T, RtFft<24>>(a); break;
+    default: launch_with<T, RtFft<40>>(a); break;
+  }
+}
+
 int round_threads(int t) { return t < 64 ? 64 : ((t + 63) / 64) * 64; }
 
 int largest_pow2_divisor_le(int n, int cap) {
@@ -719,9 +396,9 @@ int largest_pow2_divisor_le(int n, int cap) {
 // FP32 (96 VGPRs of data); EQ_X6=0/1 overrides (FP64 E = 8 doubles that).
 template <typename T>
 bool use_x6(const AxisFft& ax) {
-  // compile-time schedules exist for the powers of two 16 .. 1024 (radix 8 then one 2/4/8)
+  // needs a compile-time radix-8 schedule (the powers of two 32 .. 512, eq_sched_pow2.hip)
   const int n = ax.d.n;
-  if (!ax.fast || ax.E != 8 || n < 16 || (n & (n - 1)) != 0) return false;
+  if (!ax.fast || ax.E != 8 || n < 32 || n > 512 || (n & (n - 1)) != 0 || !ct_enabled()) return false;
   const char* e = std::getenv("EQ_X6");
   if (e) return e[0] == '1';
   return sizeof(T) == 4;
@@ -776,8 +453,10 @@ int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
     return rw;
   }
   if (ax.fast) {
+    // one line per thread group: about 128 threads per workgroup (several rows when lines are short)
     const int ls = g.nx + g.nx / 16 + 1;
-    int rw = 1;
+    int rw = 128 / (6 * P);
+    if (rw < 1) rw = 1;
     while (rw > 1 && (6 * rw * P > kMaxFastThreads || (size_t)6 * rw * ls * eb > kLdsPreferred)) --rw;
     return rw;
   }
@@ -808,19 +487,28 @@ hipError_t launch_tables(const Geom& g, int op, double h, double* sym, double2* 
   return hipGetLastError();
 }
 
-#define EQ_FAST_E_SWITCH(E_, BODY) \
-  switch (E_) {                    \
-    case 8: { constexpr int EE = 8; BODY; } break;   \
-    case 16: { constexpr int EE = 16; BODY; } break; \
-    case 24: { constexpr int EE = 24; BODY; } break; \
-    default: { constexpr int EE = 40; BODY; } break; \
-  }
 #define EQ_GEN_E_SWITCH(E_, BODY)  \
   switch (E_) {                    \
     case 8: { constexpr int EE = 8; BODY; } break;   \
     case 4: { constexpr int EE = 4; BODY; } break;   \
     default: { constexpr int EE = 2; BODY; } break;  \
   }
+
+template <typename T>
+FastArgs<T> fast_args(KernelKind kind, const AxisFft& ax, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                      const cplx<T>* tw) {
+  FastArgs<T> f;
+  f.kind = kind;
+  f.n = ax.d.n;
+  f.E = ax.E;
+  f.grid = grid;
+  f.block = block;
+  f.lds = lds;
+  f.s = s;
+  f.d = ax.d;
+  f.tw = tw;
+  return f;
+}
 
 template <typename T>
 hipError_t launch_z_r2c(const T* in, cplx<T>* W, const Geom& g, const AxisFft& az, const cplx<T>* tw_z,
@@ -832,8 +520,11 @@ hipError_t launch_z_r2c(const T* in, cplx<T>* W, const Geom& g, const AxisFft& a
   const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.ny * g.batch * 6));
   const int P = g.nz / az.E;
   if (az.fast) {
-    const dim3 block((tx / 2) * P);
-    EQ_FAST_E_SWITCH(az.E, hipLaunchKernelGGL((k_z_r2c_r<T, EE>), grid, block, lds, s, in, W, a, az.d, tw_z));
+    FastArgs<T> f = fast_args<T>(KK_Z_R2C, az, grid, dim3((tx / 2) * P), lds, s, tw_z);
+    f.in = in;
+    f.W = W;
+    f.za = a;
+    dispatch_fast<T>(f);
   } else {
     const dim3 block(round_threads((tx / 2) * P));
     EQ_GEN_E_SWITCH(az.E, hipLaunchKernelGGL((k_z_r2c_g<T, EE>), grid, block, lds, s, in, W, a, az.d, tw_z));
@@ -851,9 +542,10 @@ hipError_t launch_y(cplx<T>* W, const Geom& g, int pl0, int npl, int ncomp, cons
   const dim3 grid((unsigned)((size_t)(g.nx / tx) * npl * ncomp));
   const int P = g.ny / ay.E;
   if (ay.fast) {
-    const dim3 block(tx * P);
-    if (inv) { EQ_FAST_E_SWITCH(ay.E, hipLaunchKernelGGL((k_y_r<T, EE, true>), grid, block, lds, s, W, a, ay.d, tw_y)); }
-    else { EQ_FAST_E_SWITCH(ay.E, hipLaunchKernelGGL((k_y_r<T, EE, false>), grid, block, lds, s, W, a, ay.d, tw_y)); }
+    FastArgs<T> f = fast_args<T>(inv ? KK_Y_INV : KK_Y_FWD, ay, grid, dim3(tx * P), lds, s, tw_y);
+    f.W = W;
+    f.ya = a;
+    dispatch_fast<T>(f);
   } else {
     const dim3 block(round_threads(tx * P));
     if (inv) { EQ_GEN_E_SWITCH(ay.E, hipLaunchKernelGGL((k_y_g<T, EE, true>), grid, block, lds, s, W, a, ay.d, tw_y)); }
@@ -872,20 +564,13 @@ hipError_t launch_x(cplx<T>* W, const Geom& g, int pl0, int npl, int mode, const
   const size_t lds = lds_x(g, ax, eb, tn);
   const dim3 grid((unsigned)((rows + rw - 1) / rw));
   const int P = g.nx / ax.E;
-  if (use_x6<T>(ax)) {
-    const dim3 block(rw * P);
-    switch (g.nx) {
-      case 16: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 2>>), grid, block, lds, s, W, a, tw_x, sym); break;
-      case 32: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 4>>), grid, block, lds, s, W, a, tw_x, sym); break;
-      case 64: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8>>), grid, block, lds, s, W, a, tw_x, sym); break;
-      case 128: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8, 2>>), grid, block, lds, s, W, a, tw_x, sym); break;
-      case 256: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8, 4>>), grid, block, lds, s, W, a, tw_x, sym); break;
-      case 512: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8, 8>>), grid, block, lds, s, W, a, tw_x, sym); break;
-      default: hipLaunchKernelGGL((k_x6_r<T, Sched<8, 8, 8, 2>>), grid, block, lds, s, W, a, tw_x, sym); break;
-    }
-  } else if (ax.fast) {
-    const dim3 block(6 * rw * P);
-    EQ_FAST_E_SWITCH(ax.E, hipLaunchKernelGGL((k_x_r<T, EE>), grid, block, lds, s, W, a, ax.d, tw_x, sym));
+  if (ax.fast) {
+    const bool six = use_x6<T>(ax);
+    FastArgs<T> f = fast_args<T>(six ? KK_X6 : KK_X, ax, grid, dim3((six ? 1 : 6) * rw * P), lds, s, tw_x);
+    f.W = W;
+    f.xa = a;
+    f.sym = sym;
+    dispatch_fast<T>(f);
   } else {
     const dim3 block(round_threads(6 * rw * P));
     EQ_GEN_E_SWITCH(ax.E, hipLaunchKernelGGL((k_x_g<T, EE>), grid, block, lds, s, W, a, ax.d, tw_x, sym));
@@ -905,9 +590,14 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
   const T scale = (T)(1.0 / ((double)g.nx * (double)g.ny * (double)g.nz));
   const int P = g.nz / az.E;
   if (az.fast) {
-    const dim3 block((tx / 2) * P);
-    EQ_FAST_E_SWITCH(az.E, hipLaunchKernelGGL((k_z_c2r_r<T, EE>), grid, block, lds, s, W, out, in, removed, a, az.d,
-                                              tw_z, scale));
+    FastArgs<T> f = fast_args<T>(KK_Z_C2R, az, grid, dim3((tx / 2) * P), lds, s, tw_z);
+    f.Wc = W;
+    f.out = out;
+    f.in = in;
+    f.removed = removed;
+    f.zca = a;
+    f.scale = scale;
+    dispatch_fast<T>(f);
   } else {
     const dim3 block(round_threads((tx / 2) * P));
     EQ_GEN_E_SWITCH(az.E, hipLaunchKernelGGL((k_z_c2r_g<T, EE>), grid, block, lds, s, W, out, in, removed, a, az.d,

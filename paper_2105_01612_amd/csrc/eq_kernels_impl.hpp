@@ -1,0 +1,446 @@
+// eq_kernels_impl.hpp -- register-engine kernels of the projection, generic over the
+// FFT policy (compile-time Sched<R...> or run-time RtFft<E>), and the launch helper
+// that instantiates them.  Included by eq_kernels.hip (run-time policies) and by the
+// eq_sched_*.hip translation units (compile-time schedules).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "eq_fft.hpp"
+#include "eq_internal.hpp"
+
+namespace eq {
+
+constexpr int kMaxThreads = 1024;      // generic-engine workgroups
+constexpr int kMaxFastThreads = 512;   // register-engine workgroups (up to 256 VGPRs per lane)
+constexpr size_t kLdsPreferred = 64 * 1024;
+
+// ----------------------------------------------------- per-frequency ops ---
+
+// Projection of one frequency: out = P A P, P = I - n n^T, n = s / |s| formed in FP64.
+// Voigt slots: 0=11 1=22 2=33 3=23 4=13 5=12.
+template <typename T>
+__device__ __forceinline__ void project_one(cplx<T>* A /*6*/, double sx, double sy, double sz) {
+  using C = cplx<T>;
+  const double ss = sx * sx + sy * sy + sz * sz;
+  if (!(ss > 0.0)) return;                                   // zero symbol: divergence-free, kept
+  const double inv = 1.0 / sqrt(ss);
+  const T n0 = (T)(sx * inv), n1 = (T)(sy * inv), n2 = (T)(sz * inv);
+  const C a00 = A[0], a11 = A[1], a22 = A[2], a12 = A[3], a02 = A[4], a01 = A[5];
+  // b = A n
+  C b0, b1, b2;
+  b0.x = a00.x * n0 + a01.x * n1 + a02.x * n2;  b0.y = a00.y * n0 + a01.y * n1 + a02.y * n2;
+  b1.x = a01.x * n0 + a11.x * n1 + a12.x * n2;  b1.y = a01.y * n0 + a11.y * n1 + a12.y * n2;
+  b2.x = a02.x * n0 + a12.x * n1 + a22.x * n2;  b2.y = a02.y * n0 + a12.y * n1 + a22.y * n2;
+  // c = n . b
+  C cc;
+  cc.x = n0 * b0.x + n1 * b1.x + n2 * b2.x;
+  cc.y = n0 * b0.y + n1 * b1.y + n2 * b2.y;
+  // out_ij = A_ij - n_i b_j - b_i n_j + c n_i n_j
+  auto upd = [&](C aij, T ni, T nj, C bi, C bj) -> C {
+    C o;
+    const T nn = ni * nj;
+    o.x = aij.x - ni * bj.x - nj * bi.x + cc.x * nn;
+    o.y = aij.y - ni * bj.y - nj * bi.y + cc.y * nn;
+    return o;
+  };
+  A[0] = upd(a00, n0, n0, b0, b0);
+  A[1] = upd(a11, n1, n1, b1, b1);
+  A[2] = upd(a22, n2, n2, b2, b2);
+  A[3] = upd(a12, n1, n2, b1, b2);
+  A[4] = upd(a02, n0, n2, b0, b2);
+  A[5] = upd(a01, n0, n1, b0, b1);
+}
+
+// Divergence of one frequency: r_i = sum_j (i s_j) A_ij, written to slots 0..2.
+template <typename T>
+__device__ __forceinline__ void divergence_one(cplx<T>* A, double sx, double sy, double sz) {
+  using C = cplx<T>;
+  const T s0 = (T)sx, s1 = (T)sy, s2 = (T)sz;
+  const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+  C r3[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const C p = A[idx[i][0]], q = A[idx[i][1]], w = A[idx[i][2]];
+    const T re = s0 * p.x + s1 * q.x + s2 * w.x;
+    const T im = s0 * p.y + s1 * q.y + s2 * w.y;
+    r3[i] = mk<T>(-im, re);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) A[i] = r3[i];
+}
+
+// ------------------------------------------------------------ arguments ----
+
+struct ZArgs {
+  int nx, ny, nz, tx;      // tx: real x-columns per workgroup (even)
+};
+
+struct ZcArgs {
+  int nx, ny, nz, tx, ncomp;
+  size_t out_field, out_comp;
+};
+
+struct YArgs {
+  int nx, ny, nzh, ncomp, tx, pl0, npl;
+};
+
+struct XArgs {
+  int nx, ny, nzh, pl0, rows, rw, mode;   // rows = planes in range * ny
+};
+
+__device__ __forceinline__ size_t y_tile_base(const YArgs& a) {
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int pll = bid % a.npl;
+  const int c = bid / a.npl;
+  const int pl = a.pl0 + pll;
+  const int b = pl / a.nzh, kz = pl - b * a.nzh;
+  return (((size_t)(b * 6 + c) * a.nzh + kz) * a.ny) * a.nx + (size_t)xt * a.tx;
+}
+
+__device__ __forceinline__ size_t x_row_base(const XArgs& a, int row, int c, int& kz, int& ky) {
+  const int pl = a.pl0 + row / a.ny;
+  ky = row - (row / a.ny) * a.ny;
+  const int b = pl / a.nzh;
+  kz = pl - b * a.nzh;
+  return (((size_t)(b * 6 + c) * a.nzh + kz) * a.ny + ky) * a.nx;
+}
+
+// ------------------------------------------------------- z passes (r2c) ----
+
+template <typename T, typename F>
+__global__ __launch_bounds__(kMaxFastThreads) void k_z_r2c_r(const T* __restrict__ in, cplx<T>* __restrict__ W, ZArgs a,
+                                                             FftDesc d, const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  constexpr int E = F::E;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int y = bid % a.ny;
+  const int bc = bid / a.ny;                        // b * 6 + c
+  const int np = a.tx >> 1;                         // complex lines (column pairs)
+  const int nz = F::len(d), nzh = nz / 2 + 1, P = nz / E;
+  const int line = threadIdx.x % np, p = threadIdx.x / np;
+  const size_t plane = (size_t)a.ny * a.nx;
+  const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx + 2 * line;
+  C v[1][E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[0][i] = *reinterpret_cast<const C*>(src + (size_t)(p + i * P) * plane);
+  const LdsMap m{1, np, 0};
+  F::template run<T, 1, false, true, false>(v, lds, m, line, 0, p, d, tw);
+  // separate the two packed columns: A = (Z + conj Zm) / 2, B = (Z - conj Zm) / 2i;
+  // thread (line, p) emits kz = p + i*P for the column pair `line`
+  C* dst = W + (size_t)bc * nzh * plane + (size_t)y * a.nx + (size_t)xt * a.tx + 2 * line;
+  const T half = (T)0.5;
+  constexpr int NU = E / 2 + 1;
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    const int kz = p + i * P;
+    if (kz < nzh) {
+      const C Z = lds[kz * np + line];
+      const C Zm = lds[(kz == 0 ? 0 : nz - kz) * np + line];
+      C* o = dst + (size_t)kz * plane;
+      o[0] = mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
+      o[1] = mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half);
+    }
+  }
+}
+
+// ------------------------------------------------------- z passes (c2r) ----
+
+template <typename T, typename F>
+__global__ __launch_bounds__(kMaxFastThreads) void k_z_c2r_r(const cplx<T>* __restrict__ W, T* out, const T* in,
+                                                             T* removed, ZcArgs a, FftDesc d,
+                                                             const cplx<T>* __restrict__ tw, T scale) {
+  using C = cplx<T>;
+  constexpr int E = F::E;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int ntx = a.nx / a.tx;
+  int bid = blockIdx.x;
+  const int xt = bid % ntx; bid /= ntx;
+  const int y = bid % a.ny; bid /= a.ny;
+  const int c = bid % a.ncomp;
+  const int b = bid / a.ncomp;
+  const int np = a.tx >> 1;
+  const int nz = F::len(d), nzh = nz / 2 + 1, nyq = nz / 2, P = nz / E;
+  const int line = threadIdx.x % np, p = threadIdx.x / np;
+  const size_t plane = (size_t)a.ny * a.nx;
+  const C* src = W + ((size_t)(b * 6 + c) * nzh) * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
+  constexpr int NU = E / 2 + 1;
+  constexpr int G = 8;                     // pairs loaded per group (bounds live registers)
+  // pack the two columns of each pair into one complex line: Z = A + i B, Z(-k) = conj A + i conj B;
+  // thread (line, p) reads kz = p + i*P of column pair `line`
+  const C* col = src + 2 * line;
+#pragma unroll
+  for (int g0 = 0; g0 < NU; g0 += G) {
+    C ab[G][2];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int kz = p + (g0 + i) * P;
+      if (g0 + i < NU && kz < nzh) {
+        const C* s = col + (size_t)kz * plane;
+        ab[i][0] = s[0];
+        ab[i][1] = s[1];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int kz = p + (g0 + i) * P;
+      if (g0 + i < NU && kz < nzh) {
+        C A = ab[i][0], B = ab[i][1];
+        if (kz == 0 || kz == nyq) { A.y = (T)0; B.y = (T)0; }   // self-conjugate planes are real
+        lds[kz * np + line] = mk<T>(A.x - B.y, A.y + B.x);
+        if (kz > 0 && kz < nyq) lds[(nz - kz) * np + line] = mk<T>(A.x + B.y, B.x - A.y);
+      }
+    }
+  }
+  __syncthreads();
+  C v[1][E];
+  const LdsMap m{1, np, 0};
+  F::template run<T, 1, true, false, true>(v, lds, m, line, 0, p, d, tw);
+  const size_t obase = (size_t)b * a.out_field + (size_t)c * a.out_comp + (size_t)y * a.nx + (size_t)xt * a.tx +
+                       2 * line;
+  if (removed) {
+    constexpr int G2 = E < 8 ? E : 8;      // input samples loaded per group
+#pragma unroll
+    for (int g0 = 0; g0 < E; g0 += G2) {
+      C s[G2];
+#pragma unroll
+      for (int i = 0; i < G2; ++i)
+        if (g0 + i < E) s[i] = *reinterpret_cast<const C*>(in + obase + (size_t)(p + (g0 + i) * P) * plane);
+#pragma unroll
+      for (int i = 0; i < G2; ++i) {
+        if (g0 + i < E) {
+          const C o = mk<T>(v[0][g0 + i].x * scale, v[0][g0 + i].y * scale);
+          const size_t off = obase + (size_t)(p + (g0 + i) * P) * plane;
+          *reinterpret_cast<C*>(removed + off) = mk<T>(s[i].x - o.x, s[i].y - o.y);
+          *reinterpret_cast<C*>(out + off) = o;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      *reinterpret_cast<C*>(out + obase + (size_t)(p + i * P) * plane) =
+          mk<T>(v[0][i].x * scale, v[0][i].y * scale);
+  }
+}
+
+// ------------------------------------------------------------- y pass ------
+
+template <typename T, typename F, bool INV>
+__global__ __launch_bounds__(kMaxFastThreads) void k_y_r(cplx<T>* __restrict__ W, YArgs a, FftDesc d,
+                                                         const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  constexpr int E = F::E;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C* base = W + y_tile_base(a);
+  const int tx = a.tx, P = F::len(d) / E;
+  const int line = threadIdx.x % tx, p = threadIdx.x / tx;
+  C* col = base + line;
+  C v[1][E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[0][i] = col[(size_t)(p + i * P) * a.nx];
+  const LdsMap m{1, tx, 0};
+  F::template run<T, 1, INV, true, true>(v, lds, m, line, 0, p, d, tw);
+#pragma unroll
+  for (int i = 0; i < E; ++i) col[(size_t)(p + i * P) * a.nx] = v[0][i];
+}
+
+// ------------------------------------------------------------- x pass ------
+
+// One line per thread group: thread (line = c * rw + r, p); the six components of a
+// frequency meet in LDS for the projection.
+template <typename T, typename F>
+__global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
+                                                         const cplx<T>* __restrict__ tw,
+                                                         const double* __restrict__ sym) {
+  using C = cplx<T>;
+  constexpr int E = F::E;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int nx = F::len(d), rw = a.rw, P = nx / E;
+  const int p = threadIdx.x % P, line = threadIdx.x / P;   // line = c * rw + r
+  const int c = line / rw, r = line - c * rw;
+  const int row0 = blockIdx.x * rw;
+  const int nrows = min(rw, a.rows - row0);
+  const bool valid = r < nrows;
+  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  const bool active = c < ncomp_out;
+  int kz, ky;
+  const size_t base = valid ? x_row_base(a, row0 + r, c, kz, ky) + p : 0;
+  C v[1][E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[0][i] = valid ? W[base + (size_t)i * P] : mk<T>((T)0, (T)0);
+  const LdsMap m{nx + nx / 16 + 1, 1, 1};
+  if (a.mode & XM_FWD) {
+    F::template run<T, 1, false, true, false>(v, lds, m, line, 0, p, d, tw);
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds[m.at(line, p + i * P)] = v[0][i];
+    __syncthreads();
+  }
+  if (a.mode & (XM_PROJ | XM_DIV)) {
+    const double* symx = sym;
+    const double* symy = sym + nx;
+    const double* symz = sym + nx + a.ny;
+    const int nthr = 6 * rw * P;
+    for (int rr = 0; rr < nrows; ++rr) {
+      int qz, qy;
+      (void)x_row_base(a, row0 + rr, 0, qz, qy);          // uniform across the workgroup
+      const double sy = symy[qy], sz = symz[qz];
+      for (int kx = threadIdx.x; kx < nx; kx += nthr) {
+        C A[6];
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc) A[cc] = lds[m.at(cc * rw + rr, kx)];
+        if (a.mode & XM_PROJ) {
+          project_one<T>(A, symx[kx], sy, sz);
+#pragma unroll
+          for (int cc = 0; cc < 6; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
+        } else {
+          divergence_one<T>(A, symx[kx], sy, sz);
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (a.mode & XM_INV) {
+    // every line takes the transform (and its barriers); lines of components a divergence
+    // pass does not output hold finite spectra and are simply not stored
+    F::template run<T, 1, true, false, true>(v, lds, m, line, 0, p, d, tw);
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[0][i] = lds[m.at(line, p + i * P)];
+  }
+  if (valid && active) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) W[base + (size_t)i * P] = v[0][i];
+  }
+}
+
+// Six-component x pass: thread (row r, p) owns elements p + i*P of all six component
+// rows, so the projection (or divergence) of each of its frequencies runs in registers
+// between the forward and inverse transforms.  LDS holds 6 * rw lines.
+template <typename T, typename F>
+__global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
+                                                          const cplx<T>* __restrict__ tw,
+                                                          const double* __restrict__ sym) {
+  using C = cplx<T>;
+  constexpr int E = F::E;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int nx = F::len(d), P = nx / E;
+  const int rw = a.rw;
+  const int p = threadIdx.x % P, r = threadIdx.x / P;
+  const int row0 = blockIdx.x * rw;
+  const bool valid = r < min(rw, a.rows - row0);
+  const size_t cstride = (size_t)a.nzh * a.ny * nx;      // between components of one field
+  int kz = 0, ky = 0;
+  const size_t base = valid ? x_row_base(a, row0 + r, 0, kz, ky) + p : 0;
+  C v[6][E];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[c][i] = valid ? W[base + c * cstride + (size_t)i * P] : mk<T>((T)0, (T)0);
+  const LdsMap m{nx + nx / 16 + 1, 1, 1};
+  if (a.mode & XM_FWD) F::template run<T, 6, false, true, true>(v, lds, m, r, rw, p, d, tw);
+  if (a.mode & (XM_PROJ | XM_DIV)) {
+    const double sy = sym[nx + ky], sz = sym[nx + a.ny + kz];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int kx = p + i * P;
+      C A[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) A[c] = v[c][i];
+      if (a.mode & XM_PROJ) project_one<T>(A, sym[kx], sy, sz);
+      else divergence_one<T>(A, sym[kx], sy, sz);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c][i] = A[c];
+    }
+  }
+  if (a.mode & XM_INV) {
+    if (a.mode & XM_FWD) __syncthreads();                  // forward's last stage read LDS
+    F::template run<T, 6, true, true, true>(v, lds, m, r, rw, p, d, tw);
+  }
+  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (c < ncomp_out)
+#pragma unroll
+        for (int i = 0; i < E; ++i) W[base + c * cstride + (size_t)i * P] = v[c][i];
+  }
+}
+
+// ------------------------------------------------------- launch helper -----
+
+enum KernelKind : int { KK_Z_R2C, KK_Z_C2R, KK_Y_FWD, KK_Y_INV, KK_X, KK_X6 };
+
+// Everything one register-engine launch needs; launch_with<T, F> issues it.
+template <typename T>
+struct FastArgs {
+  KernelKind kind;
+  int n, E;                     // line length and elements per thread of the pass's axis
+  dim3 grid, block;
+  size_t lds;
+  hipStream_t s;
+  FftDesc d;
+  const cplx<T>* tw;
+  // z_r2c
+  const T* in = nullptr;
+  cplx<T>* W = nullptr;
+  ZArgs za{};
+  // z_c2r
+  const cplx<T>* Wc = nullptr;
+  T* out = nullptr;
+  T* removed = nullptr;
+  ZcArgs zca{};
+  T scale = (T)1;
+  // y / x
+  YArgs ya{};
+  XArgs xa{};
+  const double* sym = nullptr;
+};
+
+template <typename T, typename F>
+void launch_with(const FastArgs<T>& a) {
+  switch (a.kind) {
+    case KK_Z_R2C:
+      hipLaunchKernelGGL((k_z_r2c_r<T, F>), a.grid, a.block, a.lds, a.s, a.in, a.W, a.za, a.d, a.tw);
+      break;
+    case KK_Z_C2R:
+      hipLaunchKernelGGL((k_z_c2r_r<T, F>), a.grid, a.block, a.lds, a.s, a.Wc, a.out, a.in, a.removed, a.zca, a.d,
+                         a.tw, a.scale);
+      break;
+    case KK_Y_FWD:
+      hipLaunchKernelGGL((k_y_r<T, F, false>), a.grid, a.block, a.lds, a.s, a.W, a.ya, a.d, a.tw);
+      break;
+    case KK_Y_INV:
+      hipLaunchKernelGGL((k_y_r<T, F, true>), a.grid, a.block, a.lds, a.s, a.W, a.ya, a.d, a.tw);
+      break;
+    case KK_X:
+      hipLaunchKernelGGL((k_x_r<T, F>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+      break;
+    default:
+      if constexpr (F::E == 8)
+        hipLaunchKernelGGL((k_x6_r<T, F>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+      break;
+  }
+}
+
+// Compile-time schedule launchers (eq_sched_*.hip); each returns false when it has no
+// schedule for (n, E).
+template <typename T> bool ct_launch_pow2(const FastArgs<T>& a);
+template <typename T> bool ct_launch_mixed(const FastArgs<T>& a);
+
+}  // namespace eq

@@ -1,0 +1,41 @@
+// eq_sched.hpp -- compile-time radix schedules for the common grid edges.  Each
+// schedule mirrors what the planner picks for that (n, E) (factor_axis in
+// eq_capi.cpp); a launch is taken here only when the run-time radix list matches.
+#pragma once
+
+#include "eq_kernels_impl.hpp"
+
+namespace eq {
+
+template <int... Rs>
+bool radices_match(const FftDesc& d) {
+  constexpr int rs[] = {Rs...};
+  if (d.nst != (int)sizeof...(Rs)) return false;
+  for (int i = 0; i < d.nst; ++i)
+    if (d.r[i] != rs[i]) return false;
+  return true;
+}
+
+template <typename T, int... Rs>
+bool try_sched(const FastArgs<T>& a) {
+  using S = Sched<Rs...>;
+  if (a.n != S::N || a.E != S::E || !radices_match<Rs...>(a.d)) return false;
+  launch_with<T, S>(a);
+  return true;
+}
+
+// powers of two: radix 8 (E = 8) and radix 16 (E = 16)
+template <typename T>
+bool ct_launch_pow2_impl(const FastArgs<T>& a) {
+  return try_sched<T, 8, 4>(a) || try_sched<T, 8, 8>(a) || try_sched<T, 8, 8, 2>(a) || try_sched<T, 8, 8, 4>(a) ||
+         try_sched<T, 8, 8, 8>(a) || try_sched<T, 16, 8>(a) || try_sched<T, 16, 16>(a) || try_sched<T, 16, 16, 2>(a);
+}
+
+// a factor 3 (E = 24) or 5 (E = 40)
+template <typename T>
+bool ct_launch_mixed_impl(const FastArgs<T>& a) {
+  return try_sched<T, 8, 4, 3>(a) || try_sched<T, 8, 8, 3>(a) || try_sched<T, 8, 8, 2, 3>(a) ||
+         try_sched<T, 8, 4, 5>(a);
+}
+
+}  // namespace eq
