@@ -141,7 +141,7 @@ Layout layout_of(const eq_desc* d) {
   const size_t nzh = (size_t)d->nz / 2 + 1;
   L.w_bytes = (size_t)d->batch * 6 * nzh * d->ny * d->nx * 2 * elem_size(d);
   const size_t ntab = (size_t)d->nx + d->ny + d->nz;
-  L.sym_bytes = ntab * sizeof(double);
+  L.sym_bytes = 2 * ntab * sizeof(double);     // symbols with h, then h-free symbols
   L.tw64_bytes = ntab * sizeof(double2);
   L.tw32_bytes = ntab * sizeof(float2);
   L.part_bytes = (size_t)d->batch * kRedBlocks * kRedWidth * sizeof(double);
@@ -191,6 +191,10 @@ struct eq_plan_s {
 };
 
 namespace {
+
+// Symbol tables: sym[0 .. nx+ny+nz) carry 1/h (divergence), the next nx+ny+nz are h-free
+// (projection).
+const double* sym_unit(const eq_plan_s* p) { return p->sym + (p->g.nx + p->g.ny + p->g.nz); }
 
 size_t spectrum_plane_elems(const eq_plan_s* p) { return (size_t)p->g.nzh * p->g.ny * p->g.nx; }
 size_t field_elems(const eq_plan_s* p) { return (size_t)p->g.nz * p->g.ny * p->g.nx; }
@@ -374,7 +378,7 @@ eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_remove
            "y_fwd launch");
     EQ_HIP(timed(
                p, P_X_PROJ,
-               [&] { return launch_x<T>(W, g, pl0, npl, XM_FWD | XM_PROJ | XM_INV, p->ax, twx, p->sym, p->tune, s); },
+               [&] { return launch_x<T>(W, g, pl0, npl, XM_FWD | XM_PROJ | XM_INV, p->ax, twx, sym_unit(p), p->tune, s); },
                frac),
            "x_proj launch");
     EQ_HIP(timed(p, P_Y_INV, [&] { return launch_y<T>(W, g, pl0, npl, 6, p->ay, twy, true, p->tune, s); }, frac),
@@ -740,7 +744,7 @@ eq_status eq_debug_project_spectrum(eq_plan_t p, void* spec) {
     using T = decltype(tag);
     using C = cplx<T>;
     const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
-    EQ_HIP(launch_x<T>(static_cast<C*>(spec), p->g, 0, p->g.batch * p->g.nzh, XM_PROJ, p->ax, tw, p->sym, p->tune,
+    EQ_HIP(launch_x<T>(static_cast<C*>(spec), p->g, 0, p->g.batch * p->g.nzh, XM_PROJ, p->ax, tw, sym_unit(p), p->tune,
                        p->stream),
            "proj_only");
     return EQ_OK;

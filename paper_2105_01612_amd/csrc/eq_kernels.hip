@@ -49,15 +49,17 @@ __global__ void k_tables(int nx, int ny, int nz, int op, double h, double* __res
     sincospi(2.0 * (double)q / (double)n, &sn, &cs);
     tw64[i] = make_double2(cs, -sn);
     tw32[i] = make_float2((float)cs, (float)(-sn));
-    // derivative symbol of the operator (Section 4.1 eq:cdo, Section 4.2 eq:diff)
-    double s;
+    // derivative symbol of the operator (Section 4.1 eq:cdo, Section 4.2 eq:diff); sym[total + i]
+    // holds the same symbol for h = 1, which the projection uses (it depends on the direction only)
+    double su;
     if (op == 0) {
       const int k = (2 * q < n) ? q : ((2 * q == n) ? 0 : q - n);
-      s = 2.0 * M_PI * (double)k / ((double)n * h);
+      su = 2.0 * M_PI * (double)k / (double)n;
     } else {
-      s = ((2 * q) % n == 0) ? 0.0 : sinpi(2.0 * (double)q / (double)n) / h;
+      su = ((2 * q) % n == 0) ? 0.0 : sinpi(2.0 * (double)q / (double)n);
     }
-    sym[i] = s;
+    sym[i] = su / h;
+    sym[total + i] = su;
   }
 }
 

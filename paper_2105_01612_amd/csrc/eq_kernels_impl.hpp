@@ -19,14 +19,24 @@ constexpr size_t kLdsPreferred = 64 * 1024;
 
 // ----------------------------------------------------- per-frequency ops ---
 
+// 1/sqrt(x) in FP64: the hardware estimate refined by two Newton steps (each squares the
+// relative error), for x in the range of |s|^2 of the h-free symbols, [1e-6, 30].
+__device__ __forceinline__ double rsqrt_fp64(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * (1.5 - 0.5 * x * r * r);
+  r = r * (1.5 - 0.5 * x * r * r);
+  return r;
+}
+
 // Projection of one frequency: out = P A P, P = I - n n^T, n = s / |s| formed in FP64.
-// Voigt slots: 0=11 1=22 2=33 3=23 4=13 5=12.
+// The symbols passed here are h-free (s * h): the projection depends on the direction
+// of s only.  Voigt slots: 0=11 1=22 2=33 3=23 4=13 5=12.
 template <typename T>
 __device__ __forceinline__ void project_one(cplx<T>* A /*6*/, double sx, double sy, double sz) {
   using C = cplx<T>;
   const double ss = sx * sx + sy * sy + sz * sz;
   if (!(ss > 0.0)) return;                                   // zero symbol: divergence-free, kept
-  const double inv = 1.0 / sqrt(ss);
+  const double inv = rsqrt_fp64(ss);
   const T n0 = (T)(sx * inv), n1 = (T)(sy * inv), n2 = (T)(sz * inv);
   const C a00 = A[0], a11 = A[1], a22 = A[2], a12 = A[3], a02 = A[4], a01 = A[5];
   // b = A n
