@@ -129,7 +129,7 @@ eq_status validate(const eq_desc* d) {
 
 size_t elem_size(const eq_desc* d) { return d->prec == EQ_FP64 ? sizeof(double) : sizeof(float); }
 
-constexpr int kRedBlocks = 512;   // reduction partial blocks per field
+constexpr int kRedBlocks = 1024;  // reduction partial records per field (upper bound on workgroups)
 
 struct Layout {
   size_t w_bytes, sym_bytes, tw64_bytes, tw32_bytes, part_bytes, red_bytes, flag_bytes;
@@ -451,7 +451,8 @@ eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out
            }),
            "div_stats launch");
   }
-  EQ_HIP(timed(p, P_REDUCE, [&] { return launch_reduce_final(p->partials, kRedBlocks, g.batch, p->red, st); }),
+  const int nred = p->desc.op == EQ_OP_DDO ? div_ddo_blocks(g, kRedBlocks) : kRedBlocks;
+  EQ_HIP(timed(p, P_REDUCE, [&] { return launch_reduce_final(p->partials, nred, g.batch, p->red, st); }),
          "reduce launch");
   std::vector<double> host((size_t)g.batch * kRedWidth);
   EQ_HIP(hipMemcpyAsync(host.data(), p->red, host.size() * sizeof(double), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");

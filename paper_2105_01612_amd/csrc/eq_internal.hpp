@@ -69,9 +69,12 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
 //   [0] sum_x |r|^2, [1] max_x |r|^2, [2..7] sum_x S_c, [8..13] sum_x S_c^2
 constexpr int kRedWidth = 14;
 
+// DDO residual; nblk_max bounds the workgroups per field (partials holds batch * nblk_max
+// records).  div_ddo_blocks returns how many it uses, for the final reduction.
 template <typename T>
-hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk, const Geom& g, double h,
+hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk_max, const Geom& g, double h,
                           hipStream_t s);
+int div_ddo_blocks(const Geom& g, int nblk_max);
 
 template <typename T>
 hipError_t launch_div_stats(const T* div, size_t div_field, size_t div_comp, const T* S, double* partials,

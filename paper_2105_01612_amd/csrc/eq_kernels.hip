@@ -238,51 +238,79 @@ __device__ __forceinline__ void block_reduce_record(double* v, double* sh /* kRe
 
 struct DArgs {
   int nx, ny, nz;
+  int tx, ty;            // xy tile of one workgroup (tx * ty == kRedThreads)
+  int tiles_x, tiles;    // tiles per plane
+  int zc;                // z chunks: a work item is (tile, z chunk)
   double inv2h;
 };
 
 // DDO divergence in real space: periodic central differences, exactly the DDO symbol.
+// A thread owns one (x, y) column of a z chunk and marches along z; the three
+// components differentiated along z (S33, S23, S13) roll through registers, so each
+// is read from memory once per voxel, and the x and y neighbours of the current
+// plane come from the lines the workgroup's own tile just brought into cache.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S, T* __restrict__ div,
                                                          double* __restrict__ partials, DArgs a) {
   __shared__ double sh[kRedWidth * kRedThreads];
   const int b = blockIdx.y;
   const size_t M = (size_t)a.nx * a.ny * a.nz;
+  const size_t sz = (size_t)a.nx * a.ny;
   const T* F = S + (size_t)b * 6 * M;
   double acc[kRedWidth];
 #pragma unroll
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
-  const size_t sx = 1, sy = (size_t)a.nx, sz = (size_t)a.nx * a.ny;
-  for (size_t v = (size_t)blockIdx.x * kRedThreads + threadIdx.x; v < M; v += (size_t)gridDim.x * kRedThreads) {
-    const int x = (int)(v % a.nx);
-    const size_t t = v / a.nx;
-    const int y = (int)(t % a.ny);
-    const int z = (int)(t / a.ny);
-    const size_t xp = (x + 1 == a.nx) ? v + 1 - (size_t)a.nx * sx : v + sx;
-    const size_t xm = (x == 0) ? v + (size_t)(a.nx - 1) * sx : v - sx;
-    const size_t yp = (y + 1 == a.ny) ? v + sy - (size_t)a.ny * sy : v + sy;
-    const size_t ym = (y == 0) ? v + (size_t)(a.ny - 1) * sy : v - sy;
-    const size_t zp = (z + 1 == a.nz) ? v + sz - (size_t)a.nz * sz : v + sz;
-    const size_t zm = (z == 0) ? v + (size_t)(a.nz - 1) * sz : v - sz;
-    auto D = [&](int c, size_t pp, size_t mm) -> double {
-      return ((double)F[c * M + pp] - (double)F[c * M + mm]) * a.inv2h;
-    };
-    // r_x = d_x S11 + d_y S12 + d_z S13, etc. (slots 0=11 1=22 2=33 3=23 4=13 5=12)
-    const double r0 = D(0, xp, xm) + D(5, yp, ym) + D(4, zp, zm);
-    const double r1 = D(5, xp, xm) + D(1, yp, ym) + D(3, zp, zm);
-    const double r2 = D(4, xp, xm) + D(3, yp, ym) + D(2, zp, zm);
-    const double m2 = r0 * r0 + r1 * r1 + r2 * r2;
-    acc[0] += m2;
-    acc[1] = fmax(acc[1], m2);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const double s = (double)F[c * M + v];
-      acc[2 + c] += s;
-      acc[8 + c] += s * s;
-    }
-    if (div) {
-      T* o = div + (size_t)b * 3 * M + v;
-      o[0] = (T)r0; o[M] = (T)r1; o[2 * M] = (T)r2;
+  const int lx = threadIdx.x % a.tx, ly = threadIdx.x / a.tx;
+  const int items = a.tiles * a.zc;
+  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    const int tile = it % a.tiles, zi = it / a.tiles;
+    const int x = (tile % a.tiles_x) * a.tx + lx;
+    const int y = (tile / a.tiles_x) * a.ty + ly;
+    const int z0 = (int)(((long)zi * a.nz) / a.zc), z1 = (int)(((long)(zi + 1) * a.nz) / a.zc);
+    if (x >= a.nx || y >= a.ny || z0 >= z1) continue;
+    // in-plane offsets, fixed along the march
+    const size_t c = (size_t)y * a.nx + x;
+    const size_t xp = (x + 1 == a.nx) ? c + 1 - a.nx : c + 1;
+    const size_t xm = (x == 0) ? c + a.nx - 1 : c - 1;
+    const size_t yp = (y + 1 == a.ny) ? c + a.nx - sz : c + a.nx;
+    const size_t ym = (y == 0) ? c + sz - a.nx : c - a.nx;
+    const T* F0 = F;
+    const T* F1 = F + M;
+    const T* F2 = F + 2 * M;
+    const T* F3 = F + 3 * M;
+    const T* F4 = F + 4 * M;
+    const T* F5 = F + 5 * M;
+    const size_t pm = (size_t)(z0 == 0 ? a.nz - 1 : z0 - 1) * sz;
+    const size_t p0 = (size_t)z0 * sz;
+    double s2m = F2[pm + c], s3m = F3[pm + c], s4m = F4[pm + c];
+    double s2c = F2[p0 + c], s3c = F3[p0 + c], s4c = F4[p0 + c];
+    for (int z = z0; z < z1; ++z) {
+      const size_t p = (size_t)z * sz;
+      const size_t pn = (size_t)(z + 1 == a.nz ? 0 : z + 1) * sz;
+      const double s2p = F2[pn + c], s3p = F3[pn + c], s4p = F4[pn + c];
+      const double s0 = F0[p + c], s1 = F1[p + c], s5 = F5[p + c];
+      // r_x = d_x S11 + d_y S12 + d_z S13, etc. (slots 0=11 1=22 2=33 3=23 4=13 5=12)
+      const double r0 = (((double)F0[p + xp] - (double)F0[p + xm]) + ((double)F5[p + yp] - (double)F5[p + ym]) +
+                         (s4p - s4m)) * a.inv2h;
+      const double r1 = (((double)F5[p + xp] - (double)F5[p + xm]) + ((double)F1[p + yp] - (double)F1[p + ym]) +
+                         (s3p - s3m)) * a.inv2h;
+      const double r2 = (((double)F4[p + xp] - (double)F4[p + xm]) + ((double)F3[p + yp] - (double)F3[p + ym]) +
+                         (s2p - s2m)) * a.inv2h;
+      const double m2 = r0 * r0 + r1 * r1 + r2 * r2;
+      acc[0] += m2;
+      acc[1] = fmax(acc[1], m2);
+      acc[2] += s0; acc[8] += s0 * s0;
+      acc[3] += s1; acc[9] += s1 * s1;
+      acc[4] += s2c; acc[10] += s2c * s2c;
+      acc[5] += s3c; acc[11] += s3c * s3c;
+      acc[6] += s4c; acc[12] += s4c * s4c;
+      acc[7] += s5; acc[13] += s5 * s5;
+      if (div) {
+        T* o = div + (size_t)b * 3 * M + p + c;
+        o[0] = (T)r0; o[M] = (T)r1; o[2 * M] = (T)r2;
+      }
+      s2m = s2c; s3m = s3c; s4m = s4c;
+      s2c = s2p; s3c = s3p; s4c = s4p;
     }
   }
   block_reduce_record(acc, sh);
@@ -608,10 +636,35 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
   return hipGetLastError();
 }
 
+static DArgs div_ddo_shape(const Geom& g, int nblk_max, double h) {
+  DArgs a{};
+  a.nx = g.nx; a.ny = g.ny; a.nz = g.nz;
+  a.tx = 64;
+  for (int t : {64, 32, 16, 8})
+    if (g.nx % t == 0) { a.tx = t; break; }
+  a.ty = kRedThreads / a.tx;
+  a.tiles_x = (g.nx + a.tx - 1) / a.tx;
+  a.tiles = a.tiles_x * ((g.ny + a.ty - 1) / a.ty);
+  // z chunks: as many as fit the partial records, at least 8 planes per march where possible
+  int zc = nblk_max / a.tiles;
+  zc = zc < 1 ? 1 : zc;
+  const int zmax = g.nz >= 16 ? g.nz / 8 : 1;
+  a.zc = zc < zmax ? zc : zmax;
+  a.inv2h = 0.5 / h;
+  return a;
+}
+
+int div_ddo_blocks(const Geom& g, int nblk_max) {
+  const DArgs a = div_ddo_shape(g, nblk_max, 1.0);
+  const int items = a.tiles * a.zc;
+  return items < nblk_max ? items : nblk_max;
+}
+
 template <typename T>
-hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk, const Geom& g, double h, hipStream_t s) {
-  DArgs a{g.nx, g.ny, g.nz, 0.5 / h};
-  hipLaunchKernelGGL((k_div_ddo<T>), dim3(nblk, g.batch), dim3(kRedThreads), 0, s, S, div_out, partials, a);
+hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk_max, const Geom& g, double h, hipStream_t s) {
+  const DArgs a = div_ddo_shape(g, nblk_max, h);
+  hipLaunchKernelGGL((k_div_ddo<T>), dim3(div_ddo_blocks(g, nblk_max), g.batch), dim3(kRedThreads), 0, s, S, div_out,
+                     partials, a);
   return hipGetLastError();
 }
 

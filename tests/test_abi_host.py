@@ -79,7 +79,7 @@ def test_footprint_matches_layout():
         es = 8 if prec == "fp64" else 4
         w = b * 6 * (n // 2 + 1) * n * n * 2 * es
         got = eq.footprint(n, n, n, b, "ddo", prec)
-        assert w <= got <= w + b * 512 * 14 * 8 + b * 14 * 8 + 3 * n * 40 + 256   # tables: 2 symbol sets + 2 twiddle sets
+        assert w <= got <= w + b * 1024 * 14 * 8 + b * 14 * 8 + 3 * n * 40 + 256   # tables: 2 symbol sets + 2 twiddle sets
     with pytest.raises(eq.EqError) as ei:
         eq.footprint(30, 31, 30)
     assert ei.value.code == "EQ_ERR_SIZE"

@@ -215,12 +215,12 @@ def test_invariants_on_gpu_output(prec):
 
 # -------------------------------------------------------------- residual ----
 
+@pytest.mark.parametrize("shape", [(16, 24, 20), (6, 10, 4), (40, 32, 96), (8, 120, 72)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("op", ["cdo", "ddo"])
-def test_residual_parity(op, prec):
+def test_residual_parity(op, prec, shape):
     eq = eqmod()
     torch = torch_mod()
-    shape = (16, 24, 20)
     nz, ny, nx = shape
     h = 0.8
     S = wl.voronoi_field(wl.FieldSpec(shape, grains=10, sigma_grain=50.0, sigma_noise=3.0, seed=5))
@@ -236,6 +236,13 @@ def test_residual_parity(op, prec):
     for g, r in zip(norms, ref):
         assert abs(g - r) <= tol * abs(r), (norms, ref)
     assert norms == norms2
+    if op == "ddo":
+        # batched residual: each field's norms equal its single-field norms bitwise
+        plan_b = eq.plan(nx, ny, nz, batch=3, op=op, prec=prec, h=h)
+        xb = torch.stack([x[0] * 1.0, x[0] * -0.5, x[0] + 3.0]) if x.dim() == 5 else torch.stack([x, -0.5 * x, x + 3.0])
+        nb = plan_b.residual(xb)
+        assert nb[0] == norms
+        plan_b.destroy()
     d = div.double().cpu().numpy()[0]
     assert np.abs(d - rdiv).max() <= tol * np.abs(rdiv).max() * 10
     plan.destroy()
