@@ -36,10 +36,13 @@ def log(*a):
 
 
 def kernel_source_digest() -> str:
+    """sha256 (first 16 hex) over every device source file (csrc/*.hip, csrc/*.hpp, sorted)."""
     h = hashlib.sha256()
-    for f in ("eq_fft.hpp", "eq_kernels.hip", "eq_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2105_01612_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2105_01612_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -92,7 +95,7 @@ def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tu
         if tune:
             from paper_2105_01612_amd.autotune import autotune
 
-            tuned = autotune(plan, x, out, rem, reps=3, use_cache=False)
+            tuned = autotune(plan, x, out, rem, reps=3, use_cache=bool(os.environ.get("EQ_AUTOTUNE_CACHE")))
             log(f"[bench] autotuned {prec} {op}: {tuned['tune']} -> {tuned['resolved']}")
         for _ in range(warmup):
             plan.project(x, out, rem)
@@ -217,6 +220,9 @@ def main():
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for slots")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune results file (read if present, else written): a profiled run reuses an "
+                         "earlier run's results instead of launching the search's trial kernels")
     ap.add_argument("--op", default="ddo", choices=["ddo", "cdo"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and CDO side runs")
@@ -224,6 +230,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 512 MiB three times (counter calibration)")
     args = ap.parse_args()
+    if args.tune_cache:
+        os.environ["EQ_AUTOTUNE_CACHE"] = os.path.abspath(args.tune_cache)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs every field on a single MI355X "
