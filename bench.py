@@ -126,7 +126,7 @@ def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tu
 
 
 def roofline(stats, workload):
-    project_passes = ("z_r2c", "y_fwd", "x_proj", "y_inv", "z_c2r")
+    project_passes = ("z_r2c", "y_fwd", "x_proj", "y_inv", "z_c2r", "plane_r2c", "z_proj", "plane_c2r", "div_ddo")
     best = None
     for name in project_passes:
         st = stats.get(name)

@@ -1,12 +1,14 @@
 """Autotuner for libeq plans: radix schedule per axis and launch shape per pass.
 
 Every knob (eq_plan_tune) affects one kind of pass only -- the z passes, the y
-passes or the x pass -- so the search is per pass:
+passes, the x pass or the three-pass z projection -- so the search is per pass:
 
-1. radix schedule: time the plan once with every axis on radix-8 stages and once
-   with every axis on radix-16 stages; each axis keeps whichever its own passes
-   ran faster with;
-2. tile shapes: sweep tx_z, tx_y and rw_x, each against its own pass time.
+1. five-pass radix schedule: time the plan once with every axis on radix-8 stages
+   and once with every axis on radix-16 stages; each axis keeps whichever its own
+   passes ran faster with;
+2. five-pass tile shapes: sweep tx_z, tx_y and rw_x, each against its own pass time;
+3. where the grid allows the three-pass schedule: sweep tc_zp against the z
+   projection's time, then keep whichever schedule projects faster in total.
 
 Times come from the plan's per-pass hipEvents (eq_plan_pass_stats) over a few
 projections of the caller's data.  Results are cached as JSON keyed by
@@ -26,6 +28,8 @@ CACHE_ENV = "EQ_AUTOTUNE_CACHE"
 Z_PASSES = ("z_r2c", "z_c2r")
 Y_PASSES = ("y_fwd", "y_inv")
 X_PASSES = ("x_proj",)
+FIVE_PASSES = Z_PASSES + Y_PASSES + X_PASSES
+THREE_PASSES = ("plane_r2c", "z_proj", "plane_c2r")
 
 
 def cache_path() -> str:
@@ -94,9 +98,9 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
             return None
         return _pass_times(plan, x, out, rem, reps)
 
-    # 1. radix schedule per axis
-    t8 = trial(radix16=0)
-    t16 = trial(radix16=7)
+    # 1. radix schedule per axis (five passes)
+    t8 = trial(radix16=0, schedule=5)
+    t16 = trial(radix16=7, schedule=5)
     mask = 0
     if t16 is not None and t8 is not None:
         if _cost(t16, X_PASSES) < _cost(t8, X_PASSES):
@@ -105,7 +109,7 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
             mask |= 2
         if _cost(t16, Z_PASSES) < _cost(t8, Z_PASSES):
             mask |= 4
-    best = {"tx_y": 0, "tx_z": 0, "rw_x": 0, "chunk": 0, "radix16": mask}
+    best = {"tx_y": 0, "tx_z": 0, "rw_x": 0, "chunk": 0, "radix16": mask, "schedule": 5, "tc_zp": 0}
     base = trial(**best)
     log = {"radix16_all8": t8, "radix16_all16": t16, "default_shapes": base}
 
@@ -123,10 +127,29 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
             if c < best_c:
                 best_v, best_c = v, c
         best[knob] = best_v
+    five = trial(**best)
+    cost5 = _cost(five, FIVE_PASSES) if five else float("inf")
+    # 3. three-pass schedule, where the grid allows it
+    three = trial(**dict(best, schedule=3))
+    if three is not None:
+        best3, c3 = dict(best, schedule=3), _cost(three, ("z_proj",))
+        for v in (1, 2, 4, 8, 16, 32):
+            t = trial(**dict(best3, tc_zp=v))
+            if t is None:
+                continue
+            c = _cost(t, ("z_proj",))
+            log[f"tc_zp={v}"] = c
+            if c < c3:
+                best3, c3 = dict(best3, tc_zp=v), c
+        t3 = trial(**best3)
+        cost3 = _cost(t3, THREE_PASSES)
+        log["project_ms_five"], log["project_ms_three"] = cost5, cost3
+        if cost3 < cost5:
+            best = best3
     plan.tune(**best)
     final = _pass_times(plan, x, out, rem, reps)
     result = {"tune": best, "resolved": plan.get_tune(), "pass_ms": final,
-              "project_ms": sum(final.get(p, 0.0) for p in Z_PASSES + Y_PASSES + X_PASSES)}
+              "project_ms": sum(final.get(p, 0.0) for p in FIVE_PASSES + THREE_PASSES)}
     if verbose:
         result["search"] = log
     if use_cache:

@@ -1,6 +1,6 @@
 """Build libeq.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2105_01612_amd.build
+    python -m paper_2105_01612_amd.build [--incremental]
 
 Compiles every translation unit under csrc/ for gfx950 and links them into
 paper_2105_01612_amd/libeq.so next to this file.
@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libeq.so")
-SOURCES = ["eq_kernels.hip", "eq_sched_pow2_f32.hip", "eq_sched_pow2_f64.hip", "eq_sched_mixed.hip", "eq_capi.cpp"]
+SOURCES = ["eq_kernels.hip", "eq_plane.hip", "eq_sched_pow2_f32.hip", "eq_sched_pow2_f64.hip", "eq_sched_mixed.hip", "eq_capi.cpp"]
 ARCH = os.environ.get("EQ_OFFLOAD_ARCH", "gfx950")
 
 
@@ -40,8 +40,20 @@ def common_flags():
     ]
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _up_to_date(src: str, obj: str) -> bool:
+    """Object newer than its source, every csrc header and the public header."""
+    if not os.path.exists(obj):
+        return False
+    deps = [os.path.join(CSRC, src), os.path.join(INCLUDE, "eq.h")]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    t = os.path.getmtime(obj)
+    return all(os.path.getmtime(d) < t for d in deps)
+
+
+def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    if incremental and _up_to_date(src, obj):
+        return obj
     cmd = [hipcc()] + common_flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
@@ -56,10 +68,11 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every translation unit (incremental: only those older than their inputs) and link."""
     os.makedirs(OBJDIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
@@ -72,4 +85,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv[1:]))

@@ -140,6 +140,11 @@ Layout layout_of(const eq_desc* d) {
   Layout L{};
   const size_t nzh = (size_t)d->nz / 2 + 1;
   L.w_bytes = (size_t)d->batch * 6 * nzh * d->ny * d->nx * 2 * elem_size(d);
+  const Geom gg{d->nx, d->ny, d->nz, (int)nzh, d->batch};
+  if (plane_route_supported(gg, d->prec == EQ_FP64)) {   // three-pass spectrum: x is the half axis
+    const size_t w3 = (size_t)d->batch * 6 * d->nz * d->ny * (d->nx / 2 + 1) * 2 * elem_size(d);
+    L.w_bytes = std::max(L.w_bytes, w3);
+  }
   const size_t ntab = (size_t)d->nx + d->ny + d->nz;
   L.sym_bytes = 2 * ntab * sizeof(double);     // symbols with h, then h-free symbols
   L.tw64_bytes = ntab * sizeof(double2);
@@ -152,11 +157,11 @@ Layout layout_of(const eq_desc* d) {
 
 enum PassId {
   P_Z_R2C = 0, P_Y_FWD, P_X_PROJ, P_Y_INV, P_Z_C2R, P_DIV_DDO, P_X_DIV, P_Y_INV3, P_Z_C2R3, P_DIV_STATS,
-  P_REDUCE, P_CHECK, P_X_FWD, P_PROJ_ONLY, P_COUNT
+  P_REDUCE, P_CHECK, P_X_FWD, P_PROJ_ONLY, P_PLANE_R2C, P_Z_PROJ, P_PLANE_C2R, P_COUNT
 };
 const char* kPassNames[P_COUNT] = {
   "z_r2c", "y_fwd", "x_proj", "y_inv", "z_c2r", "div_ddo", "x_div", "y_inv3", "z_c2r3", "div_stats",
-  "reduce_final", "check_finite", "x_fwd", "proj_only"};
+  "reduce_final", "check_finite", "x_fwd", "proj_only", "plane_r2c", "z_proj", "plane_c2r"};
 
 struct TimingRec { int pass; hipEvent_t a, b; };
 
@@ -196,6 +201,14 @@ namespace {
 // (projection).
 const double* sym_unit(const eq_plan_s* p) { return p->sym + (p->g.nx + p->g.ny + p->g.nz); }
 
+// Whether eq_project takes the three-pass route under tuning tn.
+bool use_plane(const eq_plan_s* p, const Tune& tn) {
+  if (tn.schedule == 5 || !plane_route_supported(p->g, p->desc.prec == EQ_FP64)) return false;
+  // default: three passes where a plane leaves the workgroup room to breathe (nx <= 128);
+  // a 256^2 FP32 plane fills a CU's registers and runs no faster than five passes
+  return tn.schedule == 3 || p->g.nx <= 128;
+}
+
 size_t spectrum_plane_elems(const eq_plan_s* p) { return (size_t)p->g.nzh * p->g.ny * p->g.nx; }
 size_t field_elems(const eq_plan_s* p) { return (size_t)p->g.nz * p->g.ny * p->g.nx; }
 
@@ -204,10 +217,14 @@ double pass_bytes(const eq_plan_s* p, int pass) {
   const double B = p->g.batch;
   const double M = (double)field_elems(p);
   const double Q = (double)spectrum_plane_elems(p) * 2 * es;   // bytes of one component's half spectrum
+  const double Q3 = (double)p->g.nz * p->g.ny * (p->g.nx / 2 + 1) * 2 * es;   // same, half along x
   switch (pass) {
     case P_Z_R2C: return B * 6 * (M * es + Q);
     case P_Y_FWD: case P_X_PROJ: case P_Y_INV: case P_X_FWD: case P_PROJ_ONLY: return B * 6 * 2 * Q;
     case P_Z_C2R: return B * 6 * (Q + M * es) + (p->last_removed ? B * 6 * 2 * M * es : 0.0);
+    case P_PLANE_R2C: return B * 6 * (M * es + Q3);
+    case P_Z_PROJ: return B * 6 * 2 * Q3;
+    case P_PLANE_C2R: return B * 6 * (Q3 + M * es) + (p->last_removed ? B * 6 * 2 * M * es : 0.0);
     case P_DIV_DDO: return B * 6 * M * es;
     case P_X_DIV: return B * (6 * Q + 3 * Q);
     case P_Y_INV3: return B * 3 * 2 * Q;
@@ -309,7 +326,17 @@ eq_status check_shapes(const eq_plan_s* p, const Tune& tn) {
     return fail(EQ_ERR_ARG, "tx_z does not fit this grid");
   if (rw < 1 || round64(thx) > max_threads(p->ax)) return fail(EQ_ERR_ARG, "rw_x does not fit this grid");
   if (tn.chunk < -1 || tn.chunk > g.batch * g.nzh) return fail(EQ_ERR_ARG, "chunk out of range");
-  const size_t need = std::max(lds_y(g, p->ay, eb, tn), std::max(lds_z(g, p->az, eb, tn), lds_x(g, p->ax, eb, tn)));
+  if (tn.schedule != 0 && tn.schedule != 3 && tn.schedule != 5) return fail(EQ_ERR_ARG, "schedule must be 0, 3 or 5");
+  const bool fp64 = p->desc.prec == EQ_FP64;
+  if (tn.schedule == 3 && !plane_route_supported(g, fp64))
+    return fail(EQ_ERR_ARG, "the three-pass schedule needs nx == ny in {64, 128, 256} (FP64: 64, 128) and nz in "
+                            "{64, 128, 256}");
+  size_t need = std::max(lds_y(g, p->ay, eb, tn), std::max(lds_z(g, p->az, eb, tn), lds_x(g, p->ax, eb, tn)));
+  if (use_plane(p, tn)) {
+    const int tc = pick_tc_zproj(g, fp64, tn.tc_zp);
+    if (tn.tc_zp < 0 || (tn.tc_zp > 0 && tc != tn.tc_zp)) return fail(EQ_ERR_ARG, "tc_zp does not fit this grid");
+    need = std::max(need, std::max(plane_lds(g, fp64), zproj_lds(g, fp64, tc)));
+  }
   if (need > (size_t)limit)
     return fail(EQ_ERR_SIZE, "grid needs " + std::to_string(need) + " B of LDS per workgroup; device allows " +
                                  std::to_string(limit));
@@ -336,6 +363,8 @@ Tune tune_from_env() {
       else if (key == "rw_x") t.rw_x = val;
       else if (key == "chunk") t.chunk = val;
       else if (key == "radix16") t.radix16 = val;
+      else if (key == "schedule") t.schedule = val;
+      else if (key == "tc_zp") t.tc_zp = val;
     }
     pos = end + 1;
   }
@@ -358,8 +387,31 @@ int chunk_planes(const eq_plan_s* p) {
 }
 
 template <typename T>
+eq_status run_project_plane(eq_plan_s* p, const void* s_in, void* s_eq, void* s_removed) {
+  using C = cplx<T>;
+  C* W = static_cast<C*>(p->W);
+  const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
+  const C* twx = tw;
+  const C* twy = tw + p->g.nx;
+  const C* twz = tw + p->g.nx + p->g.ny;
+  const Geom& g = p->g;
+  hipStream_t s = p->stream;
+  const int tc = pick_tc_zproj(g, p->desc.prec == EQ_FP64, p->tune.tc_zp);
+  EQ_HIP(timed(p, P_PLANE_R2C, [&] { return launch_plane_r2c<T>(static_cast<const T*>(s_in), W, g, twx, twy, s); }),
+         "plane_r2c launch");
+  EQ_HIP(timed(p, P_Z_PROJ, [&] { return launch_zproj<T>(W, g, twz, sym_unit(p), tc, s); }), "z_proj launch");
+  EQ_HIP(timed(p, P_PLANE_C2R, [&] {
+           return launch_plane_c2r<T>(W, static_cast<T*>(s_eq), static_cast<const T*>(s_in), static_cast<T*>(s_removed),
+                                      g, twx, twy, s);
+         }),
+         "plane_c2r launch");
+  return EQ_OK;
+}
+
+template <typename T>
 eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_removed) {
   using C = cplx<T>;
+  if (use_plane(p, p->tune)) return run_project_plane<T>(p, s_in, s_eq, s_removed);
   C* W = static_cast<C*>(p->W);
   const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
   const C* twx = tw;
@@ -652,6 +704,8 @@ eq_status eq_plan_tune(eq_plan_t p, const eq_tune* tv) {
   Tune t;
   t.tx_y = tv->tx_y; t.tx_z = tv->tx_z; t.rw_x = tv->rw_x; t.chunk = tv->chunk;
   t.radix16 = tv->radix16;
+  t.schedule = tv->schedule;
+  t.tc_zp = tv->tc_zp;
   DeviceGuard dg(p->device);
   const AxisFft ax = p->ax, ay = p->ay, az = p->az;
   set_axes(p, t.radix16);
@@ -674,6 +728,9 @@ eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t) {
   t->rw_x = pick_rw_x(p->g, p->ax, eb, p->tune);
   t->chunk = chunk_planes(p);
   t->radix16 = (p->ax.E == 16 ? 1 : 0) | (p->ay.E == 16 ? 2 : 0) | (p->az.E == 16 ? 4 : 0);
+  const bool plane = use_plane(p, p->tune);
+  t->schedule = plane ? 3 : 5;
+  t->tc_zp = plane ? pick_tc_zproj(p->g, p->desc.prec == EQ_FP64, p->tune.tc_zp) : 0;
   return EQ_OK;
 }
 

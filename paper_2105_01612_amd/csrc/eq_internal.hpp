@@ -30,6 +30,8 @@ struct Tune {
   int rw_x = 0;    // rows per workgroup of the fused x pass
   int chunk = 0;   // planes per chunk of the y/x/y sequence (0 = library default, -1 = no chunking)
   int radix16 = -1;  // axes (1 = x, 2 = y, 4 = z) using radix-16 schedules; -1 = default (y)
+  int schedule = 0;  // 5 = five passes, 3 = three passes (plane route), 0 = default
+  int tc_zp = 0;     // columns per workgroup of the three-pass z projection
 };
 
 // Modes of the fused x pass.
@@ -86,6 +88,23 @@ template <typename T>
 hipError_t launch_check_finite(const T* in, size_t n, int* flag, hipStream_t s);
 
 hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s);
+
+// Three-pass schedule (eq_plane.hip).  Spectrum workspace W2 = (batch, 6, nz, ny, nx/2 + 1)
+// complex; a plane is (field, component, z).
+bool plane_route_supported(const Geom& g, bool fp64);
+size_t plane_lds(const Geom& g, bool fp64);
+int pick_tc_zproj(const Geom& g, bool fp64, int want);
+size_t zproj_lds(const Geom& g, bool fp64, int tc);
+
+template <typename T>
+hipError_t launch_plane_r2c(const T* in, cplx<T>* W2, const Geom& g, const cplx<T>* twx, const cplx<T>* twy,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_zproj(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, hipStream_t s);
+// out, removed (nullable): field layout; removed = in - out
+template <typename T>
+hipError_t launch_plane_c2r(const cplx<T>* W2, T* out, const T* in, T* removed, const Geom& g, const cplx<T>* twx,
+                            const cplx<T>* twy, hipStream_t s);
 
 // Launch shapes (exposed so the plan can check LDS against the device limit).
 int pick_tx_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);

@@ -1,0 +1,493 @@
+// eq_plane.hip -- three-pass schedule of the projection for grids whose xy plane of
+// one component fits one workgroup (registers + LDS):
+//
+//   plane_r2c : per (field, component, z) plane: real-to-complex DFT along x, complex
+//               DFT along y  ->  W2(b, c, z, ky, kx), kx in [0, nx/2]
+//   zproj     : per (ky, kx) column: DFT along z of all six components, projection
+//               P A P per frequency in registers, inverse DFT along z
+//   plane_c2r : per plane: inverse DFT along y, complex-to-real along x, 1/N scaling,
+//               removed = in - out
+//
+// Each pass reads and writes the field or its half spectrum once, so the projection
+// moves three round trips of HBM instead of five.  The forward and inverse DFTs are
+// the unnormalized analysis/synthesis pair of Section 3 (eqnFFT/eqniFFT, with the
+// 1/N^3 on the synthesis side); the per-frequency projection is Theorem 2 in the
+// P A P form (Section 3, eq:sequil with the gauge of eqnELH).
+//
+// Real-to-complex along x packs rows 2j and 2j+1 of a plane into one complex line,
+// z = a + i b, and separates the two half spectra from Z(k) and Z(n - k).  Columns
+// kx = 0 and kx = nx/2 of the x spectrum hold real values per row; they travel
+// through the y DFT packed as one complex column (DC + i Nyquist) and are separated
+// the same way.  The inverse path undoes both packings.
+#include <hip/hip_runtime.h>
+
+#include "eq_fft.hpp"
+#include "eq_internal.hpp"
+#include "eq_kernels_impl.hpp"
+
+namespace eq {
+namespace {
+
+// Thread maps.  x phase: thread (px, lx) owns elements x = px + i*PX of packed lines
+// j = lx + r*LX (r < RX); its x DFT leaves Z_j(k), k = px + i*PX, in registers.  y phase:
+// round ry handles half-spectrum columns kx in [ry*LY, ry*LY + LY); thread (cy, py) owns
+// rows y = py + i*PY of column kx = ry*LY + cy.  Between the two, a round's columns pass
+// through an LDS tile (ZA: Z_j(kx), ZB: Z_j(nx - kx), with ZB at kx = 0 holding the
+// Nyquist Z_j(nx/2)); the inverse kernel runs the same maps backwards with a tile of
+// real-row spectra.
+template <typename T, int NX, int NY, int NT, typename FX, typename FY>
+struct PlaneShape {
+  static constexpr int EX = FX::E, PX = NX / EX, LX = NT / PX, RX = (NY / 2) / LX;
+  static constexpr int EY = FY::E, PY = NY / EY, LY = NT / PY, RY = (NX / 2) / LY;
+  static constexpr int NXH = NX / 2 + 1, NJ = NY / 2;
+  static constexpr int LSX = NX + NX / 16 + 1;       // LDS stride of one x line (skewed)
+  static constexpr int TS = LY + 1;                  // LDS stride of one tile row
+  // forward: ZA, ZB (NJ rows each), y exchange (LY columns), column-0 buffer (NY);
+  // inverse: tile of NY rows, y exchange.  The x exchange overlaps either.
+  static constexpr int YOFF = 2 * NJ * TS;
+  static constexpr int COFF = YOFF + NY * LY;
+  static constexpr int lds_fwd = COFF + NY;
+  static constexpr size_t lds_elems = (size_t)(LX * LSX > lds_fwd ? LX * LSX : lds_fwd);
+  static_assert(FX::N == NX && FY::N == NY, "schedule length");
+  static_assert(LX * PX == NT && RX * LX == NY / 2, "x phase must tile the plane");
+  static_assert(LY * PY == NT && RY * LY == NX / 2, "y phase must tile the half spectrum");
+  static_assert(PY % 2 == 0, "rows 2j and 2j+1 of one y-column belong to neighbouring threads");
+};
+
+template <typename T, int NX, int NY, int NT, typename FX, typename FY>
+__global__ __launch_bounds__(NT) void k_plane_r2c(const T* __restrict__ in, cplx<T>* __restrict__ W2,
+                                                  const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy) {
+  using C = cplx<T>;
+  using S = PlaneShape<T, NX, NY, NT, FX, FY>;
+  constexpr int EX = S::EX, PX = S::PX, LX = S::LX, RX = S::RX;
+  constexpr int EY = S::EY, PY = S::PY, LY = S::LY, RY = S::RY, NXH = S::NXH, TS = S::TS;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C* ZA = lds;
+  C* ZB = lds + S::NJ * TS;
+  C* YX = lds + S::YOFF;
+  C* CB = lds + S::COFF;
+  const FftDesc dd{};
+  const T* src = in + (size_t)blockIdx.x * (NX * NY);
+  C* dst = W2 + (size_t)blockIdx.x * (NXH * NY);
+  const int tid = threadIdx.x;
+  const int px = tid % PX, lx = tid / PX;
+  // ---- x phase: packed line j = lx + r*LX holds rows 2j (real part) and 2j+1 (imaginary part)
+  C v[RX][EX];
+  const LdsMap mx{S::LSX, 1, 1};
+#pragma unroll
+  for (int r = 0; r < RX; ++r) {
+    const T* row = src + (size_t)(2 * (lx + r * LX)) * NX + px;
+#pragma unroll
+    for (int i = 0; i < EX; ++i) v[r][i] = mk<T>(row[i * PX], row[NX + i * PX]);
+    FX::template run<T, 1, false, true, true>(&v[r], lds, mx, lx, 0, px, dd, twx);
+    __syncthreads();
+  }
+  // ---- y phase
+  const int cy = tid % LY, py = tid / LY;
+  const LdsMap my{1, LY, 0};
+  const T half = (T)0.5;
+#pragma unroll
+  for (int ry = 0; ry < RY; ++ry) {
+    const int c0 = ry * LY;
+#pragma unroll
+    for (int r = 0; r < RX; ++r)
+#pragma unroll
+      for (int i = 0; i < EX; ++i) {
+        // addresses stay affine in (px, lx) per (r, i): one base register serves every store
+        const int k = px + i * PX, j = lx + r * LX;
+        if (k >= c0 && k < c0 + LY) ZA[j * TS + k - c0] = v[r][i];
+        if (i == NX / (2 * PX) && px == 0) {
+          if (c0 == 0) ZB[j * TS] = v[r][i];               // Nyquist Z_j(nx/2) rides in column 0
+        } else if (NX - k >= c0 && NX - k < c0 + LY) {
+          ZB[j * TS + (NX - k) - c0] = v[r][i];             // k = 0 gives nx - k = nx: never stored
+        }
+      }
+    __syncthreads();
+    const int kx = c0 + cy;
+    C u[1][EY];
+#pragma unroll
+    for (int i = 0; i < EY; ++i) {
+      const int y = py + i * PY;
+      const C Z = ZA[(y >> 1) * TS + cy], Zm = ZB[(y >> 1) * TS + cy];
+      if (kx == 0) {
+        // DC and Nyquist of a real row are real: carry them as (DC, Nyquist)
+        u[0][i] = (y & 1) ? mk<T>(Z.y, Zm.y) : mk<T>(Z.x, Zm.x);
+      } else {
+        u[0][i] = (y & 1) ? mk<T>((Z.y + Zm.y) * half, (Zm.x - Z.x) * half)
+                          : mk<T>((Z.x + Zm.x) * half, (Z.y - Zm.y) * half);
+      }
+    }
+    FY::template run<T, 1, false, true, true>(u, YX, my, cy, 0, py, dd, twy);
+    if (kx != 0) {
+#pragma unroll
+      for (int i = 0; i < EY; ++i) dst[(size_t)(py + i * PY) * NXH + kx] = u[0][i];
+    }
+    if (ry == 0) {
+      // column 0 carries DC + i Nyquist: separate the two (Hermitian) spectra
+      if (kx == 0) {
+#pragma unroll
+        for (int i = 0; i < EY; ++i) CB[py + i * PY] = u[0][i];
+      }
+      __syncthreads();
+      if (kx == 0) {
+#pragma unroll
+        for (int i = 0; i < EY; ++i) {
+          const int ky = py + i * PY;
+          const C Y = u[0][i], Ym = CB[ky == 0 ? 0 : NY - ky];
+          C* o = dst + (size_t)ky * NXH;
+          o[0] = mk<T>((Y.x + Ym.x) * half, (Y.y - Ym.y) * half);
+          o[NX / 2] = mk<T>((Y.y + Ym.y) * half, (Ym.x - Y.x) * half);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int NX, int NY, int NT, typename FX, typename FY>
+__global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2, T* __restrict__ out,
+                                                  const T* __restrict__ in, T* __restrict__ removed,
+                                                  const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
+                                                  T scale) {
+  using C = cplx<T>;
+  using S = PlaneShape<T, NX, NY, NT, FX, FY>;
+  constexpr int EX = S::EX, PX = S::PX, LX = S::LX, RX = S::RX;
+  constexpr int EY = S::EY, PY = S::PY, LY = S::LY, RY = S::RY, NXH = S::NXH, TS = S::TS;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C* TT = lds;                     // NY rows x LY columns of the round's real-row spectra
+  C* YX = lds + S::YOFF;
+  const FftDesc dd{};
+  const C* src = W2 + (size_t)blockIdx.x * (NXH * NY);
+  const size_t obase = (size_t)blockIdx.x * (NX * NY);
+  const int tid = threadIdx.x;
+  const int px = tid % PX, lx = tid / PX;
+  const int cy = tid % LY, py = tid / LY;
+  const LdsMap my{1, LY, 0};
+  C v[RX][EX];
+  // ---- y phase (inverse): column 0 packs the DC and Nyquist columns as DC + i Nyquist
+#pragma unroll
+  for (int ry = 0; ry < RY; ++ry) {
+    const int c0 = ry * LY, kx = c0 + cy;
+    C u[1][EY];
+#pragma unroll
+    for (int i = 0; i < EY; ++i) {
+      const int ky = py + i * PY;
+      const C* s = src + (size_t)ky * NXH;
+      if (kx == 0) {
+        C F0 = s[0], FN = s[NX / 2];
+        if (ky == 0 || 2 * ky == NY) { F0.y = (T)0; FN.y = (T)0; }   // self-conjugate rows are real
+        u[0][i] = mk<T>(F0.x - FN.y, F0.y + FN.x);
+      } else {
+        u[0][i] = s[kx];
+      }
+    }
+    FY::template run<T, 1, true, true, true>(u, YX, my, cy, 0, py, dd, twy);
+#pragma unroll
+    for (int i = 0; i < EY; ++i) TT[(py + i * PY) * TS + cy] = u[0][i];
+    __syncthreads();
+    // x owners gather Z_j(k) = A(k) + i B(k) (rows 2j, 2j+1) for their k in this round
+#pragma unroll
+    for (int r = 0; r < RX; ++r)
+#pragma unroll
+      for (int i = 0; i < EX; ++i) {
+        // column holding k: k itself below nx/2, nx - k above, column 0 for the Nyquist;
+        // which case applies is fixed by i except for px == 0 at i*PX == nx/2
+        const int k = px + i * PX, j = lx + r * LX;
+        const C* t0 = TT + (2 * j) * TS - c0;
+        const C* t1 = t0 + TS;
+        if (2 * i * PX < NX) {
+          if (k >= c0 && k < c0 + LY) {
+            const C A = t0[k], B = t1[k];
+            v[r][i] = (k == 0) ? mk<T>(A.x, B.x) : mk<T>(A.x - B.y, A.y + B.x);
+          }
+        } else if (2 * i * PX == NX && px == 0) {
+          if (c0 == 0) {
+            const C A = t0[0], B = t1[0];
+            v[r][i] = mk<T>(A.y, B.y);
+          }
+        } else if (NX - k >= c0 && NX - k < c0 + LY) {
+          const C A = t0[NX - k], B = t1[NX - k];
+          v[r][i] = mk<T>(A.x + B.y, B.x - A.y);
+        }
+      }
+    __syncthreads();
+  }
+  // ---- x phase (inverse): real part -> row 2j, imaginary part -> row 2j+1
+  const LdsMap mx{S::LSX, 1, 1};
+#pragma unroll
+  for (int r = 0; r < RX; ++r) {
+    FX::template run<T, 1, true, true, true>(&v[r], lds, mx, lx, 0, px, dd, twx);
+    const size_t row = obase + (size_t)(2 * (lx + r * LX)) * NX + px;
+    if (removed) {
+      T a[EX], b[EX];
+#pragma unroll
+      for (int i = 0; i < EX; ++i) { a[i] = in[row + i * PX]; b[i] = in[row + NX + i * PX]; }
+#pragma unroll
+      for (int i = 0; i < EX; ++i) {
+        const T o0 = v[r][i].x * scale, o1 = v[r][i].y * scale;
+        out[row + i * PX] = o0;
+        out[row + NX + i * PX] = o1;
+        removed[row + i * PX] = a[i] - o0;
+        removed[row + NX + i * PX] = b[i] - o1;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < EX; ++i) {
+        out[row + i * PX] = v[r][i].x * scale;
+        out[row + NX + i * PX] = v[r][i].y * scale;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ z pass -------
+
+// Raw buffer access (gfx9 resource word 3: 32-bit data format, no swizzle); the range
+// in the resource is the field's byte size.
+constexpr int kBufWord3 = 0x00020000;
+
+template <typename T>
+__device__ __forceinline__ cplx<T> buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  cplx<T> v;
+  if constexpr (sizeof(T) == 4) {
+    const auto raw = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    __builtin_memcpy(&v, &raw, sizeof(v));
+  } else {
+    const auto raw = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    __builtin_memcpy(&v, &raw, sizeof(v));
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, cplx<T> v) {
+  if constexpr (sizeof(T) == 4) {
+    decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) raw;
+    __builtin_memcpy(&raw, &v, sizeof(v));
+    __builtin_amdgcn_raw_buffer_store_b64(raw, r, voff, soff, 0);
+  } else {
+    decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) raw;
+    __builtin_memcpy(&raw, &v, sizeof(v));
+    __builtin_amdgcn_raw_buffer_store_b128(raw, r, voff, soff, 0);
+  }
+}
+
+struct ZpArgs {
+  int nx, ny, nz, nxh, tc;   // tc: columns per workgroup (divides ny * nxh)
+};
+
+// Thread (col, p) owns elements kz = p + i*P of the six component columns of one
+// (ky, kx); the forward DFTs, the projection and the inverse DFTs run in registers,
+// with the LDS exchanges of consecutive transforms alternating between two regions.
+template <typename T, typename FZ>
+__global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__ W2, ZpArgs a,
+                                                           const cplx<T>* __restrict__ tw,
+                                                           const double* __restrict__ sym) {
+  using C = cplx<T>;
+  constexpr int E = FZ::E, NZ = FZ::N, P = NZ / E;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const FftDesc dd{};
+  const int plane = a.ny * a.nxh;
+  const int ntile = plane / a.tc;
+  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range of
+  // tiles so that neighbouring narrow tiles share the 128-byte lines of their L2
+  int bid = blockIdx.x;
+  if ((gridDim.x & 7) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  const int tile = bid % ntile, b = bid / ntile;
+  const int col = threadIdx.x % a.tc, p = threadIdx.x / a.tc;
+  const int f = tile * a.tc + col;
+  const int ky = f / a.nxh, kx = f - ky * a.nxh;
+  // element (c, kz = p + i*P) sits at this thread's byte offset (a VGPR) plus a
+  // workgroup-uniform offset for (c, i) (an SGPR): buffer instructions take both, so
+  // the 6*E addresses cost no registers of their own
+  const unsigned fbytes = (unsigned)(6 * NZ) * (unsigned)plane * (unsigned)sizeof(C);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(W2 + (size_t)b * 6 * NZ * plane, 0, fbytes, kBufWord3);
+  const unsigned voff = (unsigned)(f + p * plane) * (unsigned)sizeof(C);
+  auto soff = [&](int c, int i) -> unsigned { return (unsigned)((c * NZ + i * P) * plane) * (unsigned)sizeof(C); };
+  C v[6][E];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[c][i] = buf_load<T>(rs, voff, soff(c, i));
+  constexpr int LS = NZ + NZ / 16 + 1;    // contiguous, skewed column lines: stage offsets fold into immediates
+  const LdsMap m{LS, 1, 1};
+  C* reg[2] = {lds, lds + (size_t)a.tc * LS};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) FZ::template run<T, 1, false, true, true>(&v[c], reg[c & 1], m, col, 0, p, dd, tw);
+  const double sx = sym[kx], sy = sym[a.nx + ky];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    C A[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) A[c] = v[c][i];
+    project_one<T>(A, sx, sy, sym[a.nx + a.ny + p + i * P]);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c][i] = A[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) FZ::template run<T, 1, true, true, true>(&v[c], reg[c & 1], m, col, 0, p, dd, tw);
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int i = 0; i < E; ++i) buf_store<T>(rs, voff, soff(c, i), v[c][i]);
+}
+
+// ------------------------------------------------------------ dispatch -----
+
+// radix-8 stages throughout (radix 16 needs more registers than a resident plane leaves)
+template <typename T, int N> struct PlaneCfg;
+template <> struct PlaneCfg<float, 64> { static constexpr int NT = 256; using FX = Sched<8, 8>; using FY = FX; };
+template <> struct PlaneCfg<float, 128> { static constexpr int NT = 512; using FX = Sched<8, 8, 2>; using FY = FX; };
+template <> struct PlaneCfg<float, 256> {
+  static constexpr int NT = 1024; using FX = Sched<8, 8, 4>; using FY = Sched<8, 8, 4>;
+};
+template <> struct PlaneCfg<double, 64> { static constexpr int NT = 256; using FX = Sched<8, 8>; using FY = FX; };
+template <> struct PlaneCfg<double, 128> { static constexpr int NT = 512; using FX = Sched<8, 8, 2>; using FY = FX; };
+template <> struct PlaneCfg<double, 256> { static constexpr int NT = 512; using FX = Sched<8, 8, 4>; using FY = FX; };
+
+// z schedules: eight elements per thread in FP32, four in FP64 (six components of them
+// stay in registers across the projection)
+template <typename T, int NZ> struct ZCfg;
+template <> struct ZCfg<float, 64> { using F = Sched<8, 8>; };
+template <> struct ZCfg<float, 128> { using F = Sched<8, 8, 2>; };
+template <> struct ZCfg<float, 256> { using F = Sched<8, 8, 4>; };
+template <> struct ZCfg<double, 64> { using F = Sched<4, 4, 4>; };
+template <> struct ZCfg<double, 128> { using F = Sched<4, 4, 4, 2>; };
+template <> struct ZCfg<double, 256> { using F = Sched<4, 4, 4, 4>; };
+
+template <typename T, int N>
+size_t plane_lds_bytes() {
+  using Cf = PlaneCfg<T, N>;
+  return PlaneShape<T, N, N, Cf::NT, typename Cf::FX, typename Cf::FY>::lds_elems * sizeof(cplx<T>);
+}
+
+// Workgroups above 64 KB of dynamic LDS need the function attribute raised first.
+hipError_t allow_lds(const void* kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T, int N>
+hipError_t plane_r2c_n(const T* in, cplx<T>* W2, const Geom& g, const cplx<T>* twx, const cplx<T>* twy,
+                       hipStream_t s) {
+  using Cf = PlaneCfg<T, N>;
+  using FX = typename Cf::FX;
+  using FY = typename Cf::FY;
+  const size_t lds = plane_lds_bytes<T, N>();
+  static const hipError_t once = allow_lds(reinterpret_cast<const void*>(&k_plane_r2c<T, N, N, Cf::NT, FX, FY>), lds);
+  if (once != hipSuccess) return once;
+  hipLaunchKernelGGL((k_plane_r2c<T, N, N, Cf::NT, FX, FY>), dim3(g.batch * 6 * g.nz), dim3(Cf::NT), lds, s, in, W2,
+                     twx, twy);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t plane_c2r_n(const cplx<T>* W2, T* out, const T* in, T* removed, const Geom& g, const cplx<T>* twx,
+                       const cplx<T>* twy, hipStream_t s) {
+  using Cf = PlaneCfg<T, N>;
+  using FX = typename Cf::FX;
+  using FY = typename Cf::FY;
+  const size_t lds = plane_lds_bytes<T, N>();
+  static const hipError_t once = allow_lds(reinterpret_cast<const void*>(&k_plane_c2r<T, N, N, Cf::NT, FX, FY>), lds);
+  if (once != hipSuccess) return once;
+  const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
+  hipLaunchKernelGGL((k_plane_c2r<T, N, N, Cf::NT, FX, FY>), dim3(g.batch * 6 * g.nz), dim3(Cf::NT), lds, s, W2, out,
+                     in, removed, twx, twy, scale);
+  return hipGetLastError();
+}
+
+template <typename T, int NZ>
+hipError_t zproj_n(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, hipStream_t s) {
+  using F = typename ZCfg<T, NZ>::F;
+  const ZpArgs a{g.nx, g.ny, g.nz, g.nx / 2 + 1, tc};
+  if ((double)6 * NZ * g.ny * a.nxh * sizeof(cplx<T>) >= 4294967296.0) return hipErrorInvalidValue;  // 32-bit offsets
+  if (tc < 1 || (g.ny * a.nxh) % tc != 0 || tc * (NZ / F::E) > kMaxFastThreads) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)tc * (NZ + NZ / 16 + 1) * sizeof(cplx<T>);
+  static const hipError_t once = allow_lds(reinterpret_cast<const void*>(&k_zproj<T, F>), 160 * 1024);
+  if (once != hipSuccess && lds > 64 * 1024) return once;
+  const int ntile = g.ny * a.nxh / tc;
+  hipLaunchKernelGGL((k_zproj<T, F>), dim3(ntile * g.batch), dim3(tc * (NZ / F::E)), lds, s, W2, a, twz, symu);
+  return hipGetLastError();
+}
+
+bool plane_edge_ok(int n) { return n == 64 || n == 128 || n == 256; }
+
+}  // namespace
+
+bool plane_route_supported(const Geom& g, bool fp64) {
+  if (g.nx != g.ny || !plane_edge_ok(g.nx) || !plane_edge_ok(g.nz)) return false;
+  return !fp64 || g.nx <= 128;      // an FP64 256^2 plane (528 KB) does not fit one CU
+}
+
+size_t plane_lds(const Geom& g, bool fp64) {
+  switch (g.nx) {
+    case 64: return fp64 ? plane_lds_bytes<double, 64>() : plane_lds_bytes<float, 64>();
+    case 128: return fp64 ? plane_lds_bytes<double, 128>() : plane_lds_bytes<float, 128>();
+    default: return fp64 ? plane_lds_bytes<double, 256>() : plane_lds_bytes<float, 256>();
+  }
+}
+
+int pick_tc_zproj(const Geom& g, bool fp64, int want) {
+  const int plane = g.ny * (g.nx / 2 + 1);
+  const int P = g.nz / (fp64 ? 4 : 8);
+  int tc = want > 0 ? want : (fp64 ? 8 : 16);     // 128-byte row segments per component
+  if (tc < 1) tc = 1;
+  while (tc > 1 && (plane % tc != 0 || tc * P > kMaxFastThreads)) tc >>= 1;
+  return tc;
+}
+
+size_t zproj_lds(const Geom& g, bool fp64, int tc) { return 2 * (size_t)tc * (g.nz + g.nz / 16 + 1) * (fp64 ? 16 : 8); }
+
+template <typename T>
+hipError_t launch_plane_r2c(const T* in, cplx<T>* W2, const Geom& g, const cplx<T>* twx, const cplx<T>* twy,
+                            hipStream_t s) {
+  switch (g.nx) {
+    case 64: return plane_r2c_n<T, 64>(in, W2, g, twx, twy, s);
+    case 128: return plane_r2c_n<T, 128>(in, W2, g, twx, twy, s);
+    case 256:
+      if constexpr (sizeof(T) == 4) return plane_r2c_n<T, 256>(in, W2, g, twx, twy, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_plane_c2r(const cplx<T>* W2, T* out, const T* in, T* removed, const Geom& g, const cplx<T>* twx,
+                            const cplx<T>* twy, hipStream_t s) {
+  switch (g.nx) {
+    case 64: return plane_c2r_n<T, 64>(W2, out, in, removed, g, twx, twy, s);
+    case 128: return plane_c2r_n<T, 128>(W2, out, in, removed, g, twx, twy, s);
+    case 256:
+      if constexpr (sizeof(T) == 4) return plane_c2r_n<T, 256>(W2, out, in, removed, g, twx, twy, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_zproj(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, hipStream_t s) {
+  switch (g.nz) {
+    case 64: return zproj_n<T, 64>(W2, g, twz, symu, tc, s);
+    case 128: return zproj_n<T, 128>(W2, g, twz, symu, tc, s);
+    case 256: return zproj_n<T, 256>(W2, g, twz, symu, tc, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_plane_r2c<float>(const float*, cplx<float>*, const Geom&, const cplx<float>*,
+                                            const cplx<float>*, hipStream_t);
+template hipError_t launch_plane_r2c<double>(const double*, cplx<double>*, const Geom&, const cplx<double>*,
+                                             const cplx<double>*, hipStream_t);
+template hipError_t launch_plane_c2r<float>(const cplx<float>*, float*, const float*, float*, const Geom&,
+                                            const cplx<float>*, const cplx<float>*, hipStream_t);
+template hipError_t launch_plane_c2r<double>(const cplx<double>*, double*, const double*, double*, const Geom&,
+                                             const cplx<double>*, const cplx<double>*, hipStream_t);
+template hipError_t launch_zproj<float>(cplx<float>*, const Geom&, const cplx<float>*, const double*, int,
+                                        hipStream_t);
+template hipError_t launch_zproj<double>(cplx<double>*, const Geom&, const cplx<double>*, const double*, int,
+                                         hipStream_t);
+
+}  // namespace eq

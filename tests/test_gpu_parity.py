@@ -49,12 +49,15 @@ def to_dev(a, prec):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
 
 
-def run_project(S, op, prec, h=1.0, removed=True, flags=0):
+def run_project(S, op, prec, h=1.0, removed=True, flags=0, schedule=None):
     eq = eqmod()
     torch = torch_mod()
     batch = S.shape[0] if S.ndim == 5 else 1
     nz, ny, nx = S.shape[-3:]
     plan = eq.plan(nx, ny, nz, batch=batch, op=op, prec=prec, h=h, flags=flags)
+    if schedule is not None:
+        plan.tune(schedule=schedule)
+        assert plan.get_tune()["schedule"] == schedule
     x = to_dev(S, prec)
     out = torch.empty_like(x)
     rem = torch.empty_like(x) if removed else None
@@ -150,6 +153,54 @@ def test_project_parity(prec, op, shape):
     assert rel_l2(got, ref) <= TOL[prec]
     tol_rem = 1e-11 if prec == "fp64" else 3e-5
     assert rel_l2(rem, ref_rem) <= tol_rem
+
+
+# Three-pass schedule (xy planes resident on one workgroup): nx == ny in {64, 128, 256}
+# (FP64 up to 128), nz in {64, 128, 256}; (nz, ny, nx) below.
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (128, 64, 64), (64, 128, 128), (256, 128, 128), (64, 256, 256)])
+def test_three_pass_parity(prec, op, shape):
+    eq = eqmod()
+    if prec == "fp64" and shape[-1] > 128:
+        plan = eq.plan(shape[2], shape[1], shape[0], op=op, prec=prec)
+        assert plan.get_tune()["schedule"] == 5           # falls back to five passes
+        with pytest.raises(eq.EqError) as ei:
+            plan.tune(schedule=3)
+        assert ei.value.code == "EQ_ERR_ARG"
+        plan.destroy()
+        return
+    say("three-pass", prec, op, shape)
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=40, sigma_grain=100.0, sigma_noise=5.0, sigma_grad=1.0,
+                                      seed=7 + sum(shape)))
+    got3, rem3 = run_project(S, op, prec, h=0.5, schedule=3)
+    Su = upcast(S, prec)
+    ref, ref_rem = O.project(Su, op, 0.5)
+    err3 = rel_l2(got3, ref)
+    say("  rel-L2 three-pass", err3)
+    assert err3 <= TOL[prec]
+    assert rel_l2(rem3, ref_rem) <= (1e-11 if prec == "fp64" else 3e-5)
+    got5, _ = run_project(S, op, prec, h=0.5, removed=False, schedule=5)
+    assert rel_l2(got5, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_three_pass_batch_and_plane_edges(prec):
+    """Batch of 2 on the three-pass route: each field equals its single-field run bitwise;
+    Nyquist-corner and DC planes (checkerboards, constants) survive exactly as the oracle says."""
+    n = 64
+    rng = np.random.default_rng(11)
+    x = np.arange(n)
+    cb = ((-1.0) ** (x[:, None, None] + x[None, :, None] + x[None, None, :]))     # (N/2, N/2, N/2) mode
+    f0 = wl.voronoi_field(wl.FieldSpec((n, n, n), grains=30, sigma_grain=100.0, sigma_noise=5.0, seed=21))
+    f1 = rng.standard_normal((6, n, n, n)) * 10.0 + cb[None] * np.array([3.0, -1.0, 2.0, 0.5, 0.0, 1.0])[:, None, None, None]
+    S = np.stack([f0, f1])
+    gotb, _ = run_project(S, "ddo", prec, removed=False, schedule=3)
+    for b in range(2):
+        single, _ = run_project(S[b], "ddo", prec, removed=False, schedule=3)
+        assert np.array_equal(single, gotb[b])
+        ref, _ = O.project(upcast(S[b], prec), "ddo")
+        assert rel_l2(gotb[b], ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -298,15 +349,17 @@ def test_aliasing_rejected():
     plan.destroy()
 
 
-def test_graph_replay_matches_eager():
-    """Captured graph replays (several, with eager work and syncs between) equal eager runs."""
+@pytest.mark.parametrize("n", [32, 64])
+def test_graph_replay_matches_eager(n):
+    """Captured graph replays (several, with eager work and syncs between) equal eager runs
+    (32^3: five-pass schedule, 64^3: three-pass)."""
     eq = eqmod()
     torch = torch_mod()
     s = torch.cuda.Stream()
-    S = wl.config_field("small")
+    S = wl.config_field("small") if n == 32 else wl.voronoi_field(wl.FieldSpec((n, n, n), grains=20, sigma_grain=100.0, sigma_noise=5.0, seed=3))
     with torch.cuda.stream(s):
-        eager = eq.plan(32, op="ddo", prec="fp32")
-        graph = eq.plan(32, op="ddo", prec="fp32", flags=["capture_graph"])
+        eager = eq.plan(n, op="ddo", prec="fp32")
+        graph = eq.plan(n, op="ddo", prec="fp32", flags=["capture_graph"])
         x = to_dev(S, "fp32")
         ref = eager.project(x)
         out = torch.empty_like(x)
@@ -336,6 +389,16 @@ def test_timing_stats():
         assert st[name]["launches"] == 3 and st[name]["total_ms"] > 0 and st[name]["bytes_per_launch"] > 0
     plan.reset_stats()
     assert plan.pass_stats()["x_proj"]["launches"] == 0
+    plan.destroy()
+    plan = eq.plan(64, op="ddo", prec="fp32")
+    x = to_dev(wl.voronoi_field(wl.FieldSpec((64, 64, 64), grains=20, sigma_grain=100.0, sigma_noise=5.0, seed=4)), "fp32")
+    plan.set_timing(True)
+    for _ in range(2):
+        plan.project(x)
+    st = plan.pass_stats()
+    for name in ("plane_r2c", "z_proj", "plane_c2r"):
+        assert st[name]["launches"] == 2 and st[name]["total_ms"] > 0 and st[name]["bytes_per_launch"] > 0
+    assert st["z_r2c"]["launches"] == 0
     plan.destroy()
 
 
