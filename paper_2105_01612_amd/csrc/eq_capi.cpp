@@ -129,6 +129,29 @@ eq_status validate(const eq_desc* d) {
 
 size_t elem_size(const eq_desc* d) { return d->prec == EQ_FP64 ? sizeof(double) : sizeof(float); }
 
+// max_q |s(q)|^2 = sum over axes of max_q s_a(q)^2, from the symbol definitions
+// (Section 4.1 for CDO, Section 4.2 for DDO).
+double symbol_max2(const eq_desc* d) {
+  double smax2 = 0.0;
+  const int dims[3] = {d->nx, d->ny, d->nz};
+  for (int a = 0; a < 3; ++a) {
+    double m = 0.0;
+    const int n = dims[a];
+    for (int q = 0; q < n; ++q) {
+      double v;
+      if (d->op == EQ_OP_CDO) {
+        const int k = (2 * q < n) ? q : ((2 * q == n) ? 0 : q - n);
+        v = 2.0 * M_PI * k / (n * d->h);
+      } else {
+        v = ((2 * q) % n == 0) ? 0.0 : std::sin(2.0 * M_PI * q / n) / d->h;
+      }
+      m = std::max(m, v * v);
+    }
+    smax2 += m;
+  }
+  return smax2;
+}
+
 constexpr int kRedBlocks = 1024;  // reduction partial records per field (upper bound on workgroups)
 
 struct Layout {
@@ -150,7 +173,7 @@ Layout layout_of(const eq_desc* d) {
   L.tw64_bytes = ntab * sizeof(double2);
   L.tw32_bytes = ntab * sizeof(float2);
   L.part_bytes = (size_t)d->batch * kRedBlocks * kRedWidth * sizeof(double);
-  L.red_bytes = (size_t)d->batch * kRedWidth * sizeof(double);
+  L.red_bytes = 0;   // the per-field records live in pinned host memory (see eq_plan)
   L.flag_bytes = 256;
   return L;
 }
@@ -180,7 +203,9 @@ struct eq_plan_s {
   double2* tw64 = nullptr;
   float2* tw32 = nullptr;
   double* partials = nullptr;
-  double* red = nullptr;
+  double* red = nullptr;        // per-field reduction records: pinned host memory ...
+  double* red_dev = nullptr;    // ... which the final reduction kernel writes through this alias
+  double smax2 = 0.0;           // max_q |s(q)|^2 of the operator's symbol (for the relative residual)
   int* flag = nullptr;
   // timing
   bool timing = false;
@@ -293,7 +318,7 @@ void release(eq_plan_s* p) {
   if (p->tw64) (void)hipFree(p->tw64);
   if (p->tw32) (void)hipFree(p->tw32);
   if (p->partials) (void)hipFree(p->partials);
-  if (p->red) (void)hipFree(p->red);
+  if (p->red) (void)hipHostFree(p->red);
   if (p->flag) (void)hipFree(p->flag);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
@@ -504,29 +529,11 @@ eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out
            "div_stats launch");
   }
   const int nred = p->desc.op == EQ_OP_DDO ? div_ddo_blocks(g, kRedBlocks) : kRedBlocks;
-  EQ_HIP(timed(p, P_REDUCE, [&] { return launch_reduce_final(p->partials, nred, g.batch, p->red, st); }),
+  EQ_HIP(timed(p, P_REDUCE, [&] { return launch_reduce_final(p->partials, nred, g.batch, p->red_dev, st); }),
          "reduce launch");
-  std::vector<double> host((size_t)g.batch * kRedWidth);
-  EQ_HIP(hipMemcpyAsync(host.data(), p->red, host.size() * sizeof(double), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
   EQ_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
-  // max_q |s(q)| per axis, from the symbol definitions (Section 4.1 / 4.2)
-  double smax2 = 0.0;
-  const int dims[3] = {g.nx, g.ny, g.nz};
-  for (int a = 0; a < 3; ++a) {
-    double m = 0.0;
-    for (int q = 0; q < dims[a]; ++q) {
-      double v;
-      const int n = dims[a];
-      if (p->desc.op == EQ_OP_CDO) {
-        const int k = (2 * q < n) ? q : ((2 * q == n) ? 0 : q - n);
-        v = 2.0 * M_PI * k / (n * p->desc.h);
-      } else {
-        v = ((2 * q) % n == 0) ? 0.0 : std::sin(2.0 * M_PI * q / n) / p->desc.h;
-      }
-      m = std::max(m, v * v);
-    }
-    smax2 += m;
-  }
+  const double* host = p->red;
+  const double smax2 = p->smax2;
   const double w[6] = {1, 1, 1, 2, 2, 2};
   for (int b = 0; b < g.batch; ++b) {
     const double* r = &host[(size_t)b * kRedWidth];
@@ -612,11 +619,18 @@ eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out) {
       (st = dev_alloc((void**)&p->tw64, L.tw64_bytes, "twiddles64")) != EQ_OK ||
       (st = dev_alloc((void**)&p->tw32, L.tw32_bytes, "twiddles32")) != EQ_OK ||
       (st = dev_alloc((void**)&p->partials, L.part_bytes, "partials")) != EQ_OK ||
-      (st = dev_alloc((void**)&p->red, L.red_bytes, "reduction")) != EQ_OK ||
       (st = dev_alloc((void**)&p->flag, L.flag_bytes, "flag")) != EQ_OK) {
     release(p);
     return st;
   }
+  // the residual's per-field records go straight to pinned, device-mapped host memory:
+  // no copy engine and no pageable staging between the last kernel and the host
+  e = hipHostMalloc((void**)&p->red, (size_t)d->batch * kRedWidth * sizeof(double),
+                    hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) { p->red = nullptr; release(p); return hip_fail(e, "hipHostMalloc(reduction records)"); }
+  e = hipHostGetDevicePointer((void**)&p->red_dev, p->red, 0);
+  if (e != hipSuccess) { release(p); return hip_fail(e, "hipHostGetDevicePointer(reduction records)"); }
+  p->smax2 = symbol_max2(d);
   e = launch_tables(p->g, d->op, d->h, p->sym, p->tw64, p->tw32, p->stream);
   if (e != hipSuccess) { release(p); return hip_fail(e, "table kernel launch"); }
   *out = p;

@@ -262,7 +262,11 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
   const int lx = threadIdx.x % a.tx, ly = threadIdx.x / a.tx;
   const int items = a.tiles * a.zc;
-  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+  // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous run of
+  // work items, so the y-halo rows of neighbouring tiles are read from its own L2
+  int lb = blockIdx.x;
+  if ((gridDim.x & 7) == 0) lb = (lb & 7) * (gridDim.x >> 3) + (lb >> 3);
+  for (int it = lb; it < items; it += gridDim.x) {
     const int tile = it % a.tiles, zi = it / a.tiles;
     const int x = (tile % a.tiles_x) * a.tx + lx;
     const int y = (tile / a.tiles_x) * a.ty + ly;
@@ -639,8 +643,9 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
 static DArgs div_ddo_shape(const Geom& g, int nblk_max, double h) {
   DArgs a{};
   a.nx = g.nx; a.ny = g.ny; a.nz = g.nz;
+  // widest x tile that divides nx (full rows at 256): long row segments, x halo in-tile
   a.tx = 64;
-  for (int t : {64, 32, 16, 8})
+  for (int t : {256, 128, 64, 32, 16, 8})
     if (g.nx % t == 0) { a.tx = t; break; }
   a.ty = kRedThreads / a.tx;
   a.tiles_x = (g.nx + a.tx - 1) / a.tx;
