@@ -141,8 +141,7 @@ eq_status eq_plan_reset_stats(eq_plan_t p);
  *            3 = three passes (xy plane, z + projection, xy plane), available when
  *            nx == ny in {64, 128, 256} (FP64: 64, 128) and nz in {64, 128, 256};
  *            0 = library default (three passes where available and nx <= 128),
- *   tc_zp    (ky, kx) columns per workgroup of the three-pass z projection (must divide
- *            ny * (nx/2 + 1)).
+ *   tc_zp    (ky, kx) columns per workgroup of the three-pass z projection (must divide ny).
  * Invalid shapes for this grid return EQ_ERR_ARG (EQ_ERR_SIZE if LDS would exceed the device
  * limit) and leave the plan unchanged.  Every setting computes the same transform; results
  * may differ only by floating-point rounding order when radix16 changes.

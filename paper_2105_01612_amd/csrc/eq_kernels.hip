@@ -483,7 +483,7 @@ int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
     int rw = 64 / P;
     if (rw < 1) rw = 1;
     const int ls = g.nx + g.nx / 16 + 1;
-    while (rw > 1 && (rw * P > kMaxFastThreads || (size_t)6 * rw * ls * eb > kLdsPreferred)) --rw;
+    while (rw > 1 && (rw * P > kMaxFastThreads || (size_t)3 * rw * ls * eb > kLdsPreferred)) --rw;
     return rw;
   }
   if (ax.fast) {
@@ -510,7 +510,8 @@ size_t lds_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
 }
 size_t lds_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
   const int ls = ax.fast ? g.nx + g.nx / 16 + 1 : g.nx + 1;
-  return (size_t)6 * pick_rw_x(g, ax, eb, tn) * ls * eb;
+  const int lines = use_x6_eb(ax, eb) ? 3 : 6;     // the six-component kernel transforms three rows at a time
+  return (size_t)lines * pick_rw_x(g, ax, eb, tn) * ls * eb;
 }
 
 // ----------------------------------------------------------- launchers -----

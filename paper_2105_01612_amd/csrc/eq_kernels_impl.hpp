@@ -340,7 +340,8 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W
 
 // Six-component x pass: thread (row r, p) owns elements p + i*P of all six component
 // rows, so the projection (or divergence) of each of its frequencies runs in registers
-// between the forward and inverse transforms.  LDS holds 6 * rw lines.
+// between the forward and inverse transforms.  The rows are transformed three
+// components at a time, so LDS holds 3 * rw lines (twice the workgroups per CU).
 template <typename T, typename F>
 __global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
                                                           const cplx<T>* __restrict__ tw,
@@ -363,7 +364,11 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ 
 #pragma unroll
     for (int i = 0; i < E; ++i) v[c][i] = valid ? W[base + c * cstride + (size_t)i * P] : mk<T>((T)0, (T)0);
   const LdsMap m{nx + nx / 16 + 1, 1, 1};
-  if (a.mode & XM_FWD) F::template run<T, 6, false, true, true>(v, lds, m, r, rw, p, d, tw);
+  if (a.mode & XM_FWD) {
+    F::template run<T, 3, false, true, true>(v, lds, m, r, rw, p, d, tw);
+    __syncthreads();                                       // the last stage read LDS
+    F::template run<T, 3, false, true, true>(v + 3, lds, m, r, rw, p, d, tw);
+  }
   if (a.mode & (XM_PROJ | XM_DIV)) {
     const double sy = sym[nx + ky], sz = sym[nx + a.ny + kz];
 #pragma unroll
@@ -380,7 +385,9 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ 
   }
   if (a.mode & XM_INV) {
     if (a.mode & XM_FWD) __syncthreads();                  // forward's last stage read LDS
-    F::template run<T, 6, true, true, true>(v, lds, m, r, rw, p, d, tw);
+    F::template run<T, 3, true, true, true>(v, lds, m, r, rw, p, d, tw);
+    __syncthreads();
+    F::template run<T, 3, true, true, true>(v + 3, lds, m, r, rw, p, d, tw);
   }
   const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
   if (valid) {

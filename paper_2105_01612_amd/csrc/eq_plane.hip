@@ -2,7 +2,9 @@
 // one component fits one workgroup (registers + LDS):
 //
 //   plane_r2c : per (field, component, z) plane: real-to-complex DFT along x, complex
-//               DFT along y  ->  W2(b, c, z, ky, kx), kx in [0, nx/2]
+//               DFT along y  ->  W2(b, c, z, ky, kx) for kx in [0, nx/2), and the Nyquist
+//               column kx = nx/2 in its own array W2N(b, c, z, ky) after W2, so that
+//               every row of W2 is a whole number of 128-byte lines
 //   zproj     : per (ky, kx) column: DFT along z of all six components, projection
 //               P A P per frequency in registers, inverse DFT along z
 //   plane_c2r : per plane: inverse DFT along y, complex-to-real along x, 1/N scaling,
@@ -39,7 +41,7 @@ template <typename T, int NX, int NY, int NT, typename FX, typename FY>
 struct PlaneShape {
   static constexpr int EX = FX::E, PX = NX / EX, LX = NT / PX, RX = (NY / 2) / LX;
   static constexpr int EY = FY::E, PY = NY / EY, LY = NT / PY, RY = (NX / 2) / LY;
-  static constexpr int NXH = NX / 2 + 1, NJ = NY / 2;
+  static constexpr int NXH = NX / 2, NJ = NY / 2;          // W2 row length (Nyquist apart)
   static constexpr int LSX = NX + NX / 16 + 1;       // LDS stride of one x line (skewed)
   static constexpr int TS = LY + 1;                  // LDS stride of one tile row
   // forward: ZA, ZB (NJ rows each), y exchange (LY columns), column-0 buffer (NY);
@@ -70,6 +72,7 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* __restrict__ in, cplx
   const FftDesc dd{};
   const T* src = in + (size_t)blockIdx.x * (NX * NY);
   C* dst = W2 + (size_t)blockIdx.x * (NXH * NY);
+  C* dstn = W2 + (size_t)gridDim.x * (NXH * NY) + (size_t)blockIdx.x * NY;   // Nyquist column
   const int tid = threadIdx.x;
   const int px = tid % PX, lx = tid / PX;
   // ---- x phase: packed line j = lx + r*LX holds rows 2j (real part) and 2j+1 (imaginary part)
@@ -135,9 +138,8 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* __restrict__ in, cplx
         for (int i = 0; i < EY; ++i) {
           const int ky = py + i * PY;
           const C Y = u[0][i], Ym = CB[ky == 0 ? 0 : NY - ky];
-          C* o = dst + (size_t)ky * NXH;
-          o[0] = mk<T>((Y.x + Ym.x) * half, (Y.y - Ym.y) * half);
-          o[NX / 2] = mk<T>((Y.y + Ym.y) * half, (Ym.x - Y.x) * half);
+          dst[(size_t)ky * NXH] = mk<T>((Y.x + Ym.x) * half, (Y.y - Ym.y) * half);
+          dstn[ky] = mk<T>((Y.y + Ym.y) * half, (Ym.x - Y.x) * half);
         }
       }
     }
@@ -159,6 +161,7 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2
   C* YX = lds + S::YOFF;
   const FftDesc dd{};
   const C* src = W2 + (size_t)blockIdx.x * (NXH * NY);
+  const C* srcn = W2 + (size_t)gridDim.x * (NXH * NY) + (size_t)blockIdx.x * NY;   // Nyquist column
   const size_t obase = (size_t)blockIdx.x * (NX * NY);
   const int tid = threadIdx.x;
   const int px = tid % PX, lx = tid / PX;
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2
       const int ky = py + i * PY;
       const C* s = src + (size_t)ky * NXH;
       if (kx == 0) {
-        C F0 = s[0], FN = s[NX / 2];
+        C F0 = s[0], FN = srcn[ky];
         if (ky == 0 || 2 * ky == NY) { F0.y = (T)0; FN.y = (T)0; }   // self-conjugate rows are real
         u[0][i] = mk<T>(F0.x - FN.y, F0.y + FN.x);
       } else {
@@ -275,7 +278,8 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 }
 
 struct ZpArgs {
-  int nx, ny, nz, nxh, tc;   // tc: columns per workgroup (divides ny * nxh)
+  int nx, ny, nz, tc;        // tc: columns per workgroup (divides ny)
+  int batch;
 };
 
 // Thread (col, p) owns elements kz = p + i*P of the six component columns of one
@@ -290,21 +294,27 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const FftDesc dd{};
-  const int plane = a.ny * a.nxh;
-  const int ntile = plane / a.tc;
+  // columns: ny * nx/2 of W2 (kx < nx/2), then ny Nyquist columns of W2N; a tile lies
+  // wholly in one of the two, so its base and column stride are workgroup-uniform
+  const int half = a.nx / 2;
+  const int ntm = a.ny * half / a.tc, ntile = ntm + a.ny / a.tc;
   // workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range of
   // tiles so that neighbouring narrow tiles share the 128-byte lines of their L2
   int bid = blockIdx.x;
   if ((gridDim.x & 7) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
   const int tile = bid % ntile, b = bid / ntile;
   const int col = threadIdx.x % a.tc, p = threadIdx.x / a.tc;
-  const int f = tile * a.tc + col;
-  const int ky = f / a.nxh, kx = f - ky * a.nxh;
+  const bool nyq = tile >= ntm;
+  const int plane = nyq ? a.ny : a.ny * half;
+  const int f = (nyq ? tile - ntm : tile) * a.tc + col;
+  const int ky = nyq ? f : f / half, kx = nyq ? half : f - (f / half) * half;
+  C* region = nyq ? W2 + (size_t)a.batch * 6 * NZ * a.ny * half : W2;
   // element (c, kz = p + i*P) sits at this thread's byte offset (a VGPR) plus a
   // workgroup-uniform offset for (c, i) (an SGPR): buffer instructions take both, so
   // the 6*E addresses cost no registers of their own
   const unsigned fbytes = (unsigned)(6 * NZ) * (unsigned)plane * (unsigned)sizeof(C);
-  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(W2 + (size_t)b * 6 * NZ * plane, 0, fbytes, kBufWord3);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(region + (size_t)b * 6 * NZ * plane, 0, fbytes, kBufWord3);
   const unsigned voff = (unsigned)(f + p * plane) * (unsigned)sizeof(C);
   auto soff = [&](int c, int i) -> unsigned { return (unsigned)((c * NZ + i * P) * plane) * (unsigned)sizeof(C); };
   C v[6][E];
@@ -402,13 +412,13 @@ hipError_t plane_c2r_n(const cplx<T>* W2, T* out, const T* in, T* removed, const
 template <typename T, int NZ>
 hipError_t zproj_n(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, hipStream_t s) {
   using F = typename ZCfg<T, NZ>::F;
-  const ZpArgs a{g.nx, g.ny, g.nz, g.nx / 2 + 1, tc};
-  if ((double)6 * NZ * g.ny * a.nxh * sizeof(cplx<T>) >= 4294967296.0) return hipErrorInvalidValue;  // 32-bit offsets
-  if (tc < 1 || (g.ny * a.nxh) % tc != 0 || tc * (NZ / F::E) > kMaxFastThreads) return hipErrorInvalidValue;
+  const ZpArgs a{g.nx, g.ny, g.nz, tc, g.batch};
+  if ((double)6 * NZ * g.ny * (g.nx / 2) * sizeof(cplx<T>) >= 4294967296.0) return hipErrorInvalidValue;  // 32-bit offsets
+  if (tc < 1 || g.ny % tc != 0 || tc * (NZ / F::E) > kMaxFastThreads) return hipErrorInvalidValue;
   const size_t lds = 2 * (size_t)tc * (NZ + NZ / 16 + 1) * sizeof(cplx<T>);
   static const hipError_t once = allow_lds(reinterpret_cast<const void*>(&k_zproj<T, F>), 160 * 1024);
   if (once != hipSuccess && lds > 64 * 1024) return once;
-  const int ntile = g.ny * a.nxh / tc;
+  const int ntile = g.ny * (g.nx / 2) / tc + g.ny / tc;
   hipLaunchKernelGGL((k_zproj<T, F>), dim3(ntile * g.batch), dim3(tc * (NZ / F::E)), lds, s, W2, a, twz, symu);
   return hipGetLastError();
 }
@@ -431,7 +441,7 @@ size_t plane_lds(const Geom& g, bool fp64) {
 }
 
 int pick_tc_zproj(const Geom& g, bool fp64, int want) {
-  const int plane = g.ny * (g.nx / 2 + 1);
+  const int plane = g.ny;      // tiles must divide the Nyquist columns too (and so every row of W2)
   const int P = g.nz / (fp64 ? 4 : 8);
   int tc = want > 0 ? want : (fp64 ? 8 : 16);     // 128-byte row segments per component
   if (tc < 1) tc = 1;
