@@ -106,6 +106,33 @@ eq_status eq_project(eq_plan_t p, const void* s_in, void* s_eq, void* s_removed)
  * Blocks until norms_host is written. */
 eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_out);
 
+/* Non-periodic sample in a zero-stress lateral buffer (Section 3.3; Section 6, experimental
+ * sample): the sample (nx0 x ny0 voxels in x and y, all nz planes, so top and bottom are
+ * periodically connected) sits at (ox, oy) inside the plan's periodic (nx, ny) box; every
+ * other voxel of the box is zero stress.  The box is projected as by eq_project and the
+ * result is returned on the sample's voxels only.
+ *   e     : 1 <= nx0, 0 <= ox, ox + nx0 <= nx (same for y), else EQ_ERR_ARG;
+ *   s_in  : device (batch, 6, nz, ny0, nx0), the plan's precision;
+ *   s_eq  : device, same shape (may equal s_in);
+ *   s_removed : nullable, same shape, s_in - s_eq; must not overlap the others.
+ * Always runs the five-pass schedule (the z passes read and write the sample in place of the
+ * box, so no box-sized field is ever stored) and never replays a captured graph.
+ * Stream-ordered and asynchronous. */
+typedef struct { int nx0, ny0, ox, oy; } eq_embed;
+eq_status eq_project_embedded(eq_plan_t p, const eq_embed* e, const void* s_in, void* s_eq, void* s_removed);
+
+/* Potential of the removed part (Section 3.2: S_exp = S_equil + (grad y + grad y^T)/2).
+ * Writes the periodic vector field y whose symmetric gradient, in the plan's operator
+ * (CDO or DDO, with spacing h), is exactly S_exp - S_equil: per frequency
+ * y = i (c n - 2 b) / |s| with n = s/|s|, b = A n, c = n.b, and y = 0 where the symbol is
+ * zero (so y has zero mean; the harmonic modes belong to S_equil).
+ *   s_in  : device (batch, 6, nz, ny, nx), the plan's precision (not modified);
+ *   y_out : device (batch, 3, nz, ny, nx), components (y_x, y_y, y_z), caller-owned;
+ *           must not overlap s_in (EQ_ERR_ARG).
+ * Uses the plan workspace (five-pass kernels); stream-ordered and asynchronous.  With
+ * EQ_F_CHECK_FINITE, synchronizes and returns EQ_ERR_NONFINITE on NaN/Inf input. */
+eq_status eq_potential(eq_plan_t p, const void* s_in, void* y_out);
+
 eq_status eq_plan_destroy(eq_plan_t p);
 
 /* Device bytes a plan for *d allocates (workspace + tables + reduction scratch),

@@ -63,6 +63,8 @@ __all__ = [
     "voigt_to_matrix", "matrix_to_voigt", "incompatibility", "project_spectrum_literal",
     "project_spectrum_pap", "project", "divergence", "divergence_central_difference",
     "residual_norms", "frobenius_dot", "frobenius_norm", "max_symbol_norm",
+    "sym_grad", "sym_grad_central_difference", "removed_potential", "potential_spectrum",
+    "embed_in_buffer", "project_embedded",
 ]
 
 # Voigt component c <-> tensor indices (i, j), 0-based with 0 = x, 1 = y, 2 = z.
@@ -235,6 +237,33 @@ def project(S: np.ndarray, op: str = "ddo", h: float = 1.0, route: str = "litera
     return Seq, S - Seq
 
 
+# ------------------------------------------------ zero-stress buffer ---------
+
+def embed_in_buffer(S: np.ndarray, box_xy, offset_xy) -> np.ndarray:
+    """Place a non-periodic sample (6, nz, ny0, nx0) at (ox, oy) inside a periodic box of
+    (nx, ny) voxels laterally, zero stress elsewhere; z keeps its extent, so top and bottom
+    are periodically connected (Section 3.3; Section 6, experimental sample)."""
+    S = np.asarray(S, dtype=np.float64)
+    nx, ny = box_xy
+    ox, oy = offset_xy
+    nz, ny0, nx0 = S.shape[1:]
+    if ox < 0 or oy < 0 or ox + nx0 > nx or oy + ny0 > ny:
+        raise ValueError("sample does not fit the box")
+    B = np.zeros((6, nz, ny, nx))
+    B[:, :, oy:oy + ny0, ox:ox + nx0] = S
+    return B
+
+
+def project_embedded(S: np.ndarray, box_xy, offset_xy, op: str = "ddo", h: float = 1.0):
+    """Equilibrate the buffered box and return (S_equil, removed) on the sample's voxels."""
+    S = np.asarray(S, dtype=np.float64)
+    nz, ny0, nx0 = S.shape[1:]
+    ox, oy = offset_xy
+    Seq, _ = project(embed_in_buffer(S, box_xy, offset_xy), op, h)
+    Seq = Seq[:, :, oy:oy + ny0, ox:ox + nx0]
+    return Seq, S - Seq
+
+
 # ------------------------------------------------------- divergence ---------
 
 def divergence(S: np.ndarray, op: str, h: float = 1.0) -> np.ndarray:
@@ -259,6 +288,63 @@ def divergence_central_difference(S: np.ndarray, h: float = 1.0) -> np.ndarray:
         return (np.roll(f, -1, axis=a) - np.roll(f, 1, axis=a)) / (2.0 * h)
 
     return np.stack([sum(d(M[i, j], j) for j in range(3)) for i in range(3)])
+
+
+# ------------------------------------------ potential of the removed part ---
+
+def sym_grad(y: np.ndarray, op: str, h: float = 1.0) -> np.ndarray:
+    """(grad y + grad y^T) / 2 of a periodic vector field y (3, nz, ny, nx) as a Voigt
+    field, each derivative by the operator's symbol (Section 4.1 / 4.2)."""
+    y = np.asarray(y, dtype=np.float64)
+    shape = y.shape[1:]
+    F = dft3(y)
+    s = _grid_symbols(op, shape, h, 0, shape[0])
+    G = np.empty((3, 3) + F.shape[1:], dtype=complex)
+    for i in range(3):
+        for j in range(3):
+            G[i, j] = 0.5j * (s[j] * F[i] + s[i] * F[j])
+    return idft3(matrix_to_voigt(G), shape)
+
+
+def sym_grad_central_difference(y: np.ndarray, h: float = 1.0) -> np.ndarray:
+    """Real-space periodic central differences (Section 4.2, eq:diff) of y, symmetrized."""
+    y = np.asarray(y, dtype=np.float64)
+    axis_of = {0: 2, 1: 1, 2: 0}
+
+    def d(f, j):
+        a = axis_of[j]
+        return (np.roll(f, -1, axis=a) - np.roll(f, 1, axis=a)) / (2.0 * h)
+
+    return np.stack([0.5 * (d(y[i], j) + d(y[j], i)) for (i, j) in VOIGT_PAIRS])
+
+
+def removed_potential(S: np.ndarray, op: str = "ddo", h: float = 1.0) -> np.ndarray:
+    """The field y of the decomposition S_exp = S_equil + (grad y + grad y^T)/2 (Section 3.2):
+    the least-squares preimage of the removed part under the symmetric gradient, with zero
+    mean.  Per frequency with a nonzero symbol s the normal equations of
+    min_y sum_ij |R_ij - (i/2)(y_i s_j + s_i y_j)|^2 are (1/2)(|s|^2 I + s s^T) y = -i R s,
+    with R the removed part's spectrum; y = 0 where s = 0.  Returns (3, nz, ny, nx)."""
+    S = np.asarray(S, dtype=np.float64)
+    shape = S.shape[1:]
+    _, removed = project(S, op, h)
+    R = voigt_to_matrix(dft3(removed))
+    s = _grid_symbols(op, shape, h, 0, shape[0])
+    return idft3(potential_spectrum(R, s), shape)
+
+
+def potential_spectrum(R: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """Per frequency: solve (1/2)(|s|^2 I + s s^T) y = -i R s where |s| > 0, else y = 0.
+    R: (3, 3, ...) symmetric spectra; s: (3, ...) symbols.  Returns (3, ...)."""
+    rhs = -1j * np.einsum("ij...,j...->i...", R, s)
+    ss = np.sum(s * s, axis=0)
+    eye = np.eye(3).reshape((3, 3) + (1,) * ss.ndim)
+    N = 0.5 * (ss[None, None] * eye + s[:, None] * s[None, :])
+    Y = np.zeros_like(rhs)
+    m = ss > 0
+    Nm = np.moveaxis(N[:, :, m], -1, 0)                    # (k, 3, 3)
+    bm = np.moveaxis(rhs[:, m], -1, 0)[..., None]          # (k, 3, 1)
+    Y[:, m] = np.moveaxis(np.linalg.solve(Nm.astype(complex), bm)[..., 0], 0, -1)
+    return Y
 
 
 def frobenius_dot(A: np.ndarray, B: np.ndarray) -> float:

@@ -35,7 +35,7 @@ exported_symbols = (
     "eq_plan", "eq_project", "eq_residual", "eq_plan_destroy", "eq_plan_footprint", "eq_status_str",
     "eq_last_error", "eq_plan_set_stream", "eq_plan_set_timing", "eq_plan_pass_stats",
     "eq_plan_reset_stats", "eq_debug_forward", "eq_debug_project_spectrum", "eq_version", "eq_plan_tune",
-    "eq_plan_get_tune",
+    "eq_plan_get_tune", "eq_potential", "eq_project_embedded",
 )
 
 
@@ -47,6 +47,10 @@ class EqDesc(ctypes.Structure):
 class EqTune(ctypes.Structure):
     _fields_ = [("tx_y", ctypes.c_int), ("tx_z", ctypes.c_int), ("rw_x", ctypes.c_int), ("chunk", ctypes.c_int),
                 ("radix16", ctypes.c_int), ("schedule", ctypes.c_int), ("tc_zp", ctypes.c_int)]
+
+
+class EqEmbed(ctypes.Structure):
+    _fields_ = [("nx0", ctypes.c_int), ("ny0", ctypes.c_int), ("ox", ctypes.c_int), ("oy", ctypes.c_int)]
 
 
 class EqError(RuntimeError):
@@ -71,6 +75,8 @@ def lib() -> ctypes.CDLL:
     L.eq_plan.argtypes = [ctypes.POINTER(EqDesc), vp, ctypes.POINTER(vp)]
     L.eq_project.argtypes = [vp, vp, vp, vp]
     L.eq_residual.argtypes = [vp, vp, dp, vp]
+    L.eq_potential.argtypes = [vp, vp, vp]
+    L.eq_project_embedded.argtypes = [vp, ctypes.POINTER(EqEmbed), vp, vp, vp]
     L.eq_plan_destroy.argtypes = [vp]
     L.eq_plan_footprint.argtypes = [ctypes.POINTER(EqDesc), ctypes.POINTER(ctypes.c_size_t)]
     L.eq_status_str.argtypes = [ip]
@@ -215,6 +221,35 @@ class Plan:
         _check(lib().eq_residual(self._h, _ptr(s, "s", self, shape), norms,
                                  _ptr(div_out, "div_out", self, dshape) or None), "eq_residual")
         return [(norms[3 * b], norms[3 * b + 1], norms[3 * b + 2]) for b in range(self.batch)]
+
+    def project_embedded(self, s_in, nx0, ny0, ox, oy, s_eq=None, s_removed=None):
+        """eq_project_embedded: s_in (batch, 6, nz, ny0, nx0) sits at (ox, oy) in this plan's
+        (nx, ny) box with zero stress around it; returns s_eq of the sample's shape."""
+        if s_eq is None:
+            import torch
+
+            s_eq = torch.empty_like(s_in)
+        shape = (self.batch, 6, self.nz, int(ny0), int(nx0))
+        if s_in.dim() == 4:
+            shape = shape[1:]
+        e = EqEmbed(int(nx0), int(ny0), int(ox), int(oy))
+        _check(lib().eq_project_embedded(self._h, ctypes.byref(e), _ptr(s_in, "s_in", self, shape),
+                                         _ptr(s_eq, "s_eq", self, shape),
+                                         _ptr(s_removed, "s_removed", self, shape) or None), "eq_project_embedded")
+        return s_eq
+
+    def potential(self, s_in, y_out=None):
+        """eq_potential: the potential y of the removed part (its symmetric gradient is
+        s_in - project(s_in)); returns y_out, shape (batch, 3, nz, ny, nx), allocated when omitted."""
+        shape = self._shape_of(s_in)
+        yshape = (self.batch, 3, self.nz, self.ny, self.nx)
+        if y_out is None:
+            import torch
+
+            y_out = torch.empty(yshape if s_in.dim() == 5 else yshape[1:], dtype=s_in.dtype, device=s_in.device)
+        _check(lib().eq_potential(self._h, _ptr(s_in, "s_in", self, shape), _ptr(y_out, "y_out", self, yshape)),
+               "eq_potential")
+        return y_out
 
     def set_stream(self, stream=None):
         """Rebind to `stream` (a torch stream or raw handle; None = torch's current stream)."""

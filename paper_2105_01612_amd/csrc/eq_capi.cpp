@@ -180,11 +180,11 @@ Layout layout_of(const eq_desc* d) {
 
 enum PassId {
   P_Z_R2C = 0, P_Y_FWD, P_X_PROJ, P_Y_INV, P_Z_C2R, P_DIV_DDO, P_X_DIV, P_Y_INV3, P_Z_C2R3, P_DIV_STATS,
-  P_REDUCE, P_CHECK, P_X_FWD, P_PROJ_ONLY, P_PLANE_R2C, P_Z_PROJ, P_PLANE_C2R, P_COUNT
+  P_REDUCE, P_CHECK, P_X_FWD, P_PROJ_ONLY, P_PLANE_R2C, P_Z_PROJ, P_PLANE_C2R, P_X_POT, P_COUNT
 };
 const char* kPassNames[P_COUNT] = {
   "z_r2c", "y_fwd", "x_proj", "y_inv", "z_c2r", "div_ddo", "x_div", "y_inv3", "z_c2r3", "div_stats",
-  "reduce_final", "check_finite", "x_fwd", "proj_only", "plane_r2c", "z_proj", "plane_c2r"};
+  "reduce_final", "check_finite", "x_fwd", "proj_only", "plane_r2c", "z_proj", "plane_c2r", "x_pot"};
 
 struct TimingRec { int pass; hipEvent_t a, b; };
 
@@ -251,7 +251,7 @@ double pass_bytes(const eq_plan_s* p, int pass) {
     case P_Z_PROJ: return B * 6 * 2 * Q3;
     case P_PLANE_C2R: return B * 6 * (Q3 + M * es) + (p->last_removed ? B * 6 * 2 * M * es : 0.0);
     case P_DIV_DDO: return B * 6 * M * es;
-    case P_X_DIV: return B * (6 * Q + 3 * Q);
+    case P_X_DIV: case P_X_POT: return B * (6 * Q + 3 * Q);
     case P_Y_INV3: return B * 3 * 2 * Q;
     case P_Z_C2R3: return B * 3 * (Q + M * es);
     case P_DIV_STATS: return B * 9 * M * es;
@@ -433,10 +433,12 @@ eq_status run_project_plane(eq_plan_s* p, const void* s_in, void* s_eq, void* s_
   return EQ_OK;
 }
 
+// e.on: the real fields are a sample embedded in the box (five passes; the z passes read
+// the sample with a zero buffer around it and write the sample's voxels only).
 template <typename T>
-eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_removed) {
+eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_removed, const Embed& e = Embed{}) {
   using C = cplx<T>;
-  if (use_plane(p, p->tune)) return run_project_plane<T>(p, s_in, s_eq, s_removed);
+  if (!e.on && use_plane(p, p->tune)) return run_project_plane<T>(p, s_in, s_eq, s_removed);
   C* W = static_cast<C*>(p->W);
   const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
   const C* twx = tw;
@@ -445,7 +447,8 @@ eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_remove
   const Geom& g = p->g;
   hipStream_t s = p->stream;
   const size_t M = field_elems(p);
-  EQ_HIP(timed(p, P_Z_R2C, [&] { return launch_z_r2c<T>(static_cast<const T*>(s_in), W, g, p->az, twz, p->tune, s); }),
+  EQ_HIP(timed(p, P_Z_R2C,
+               [&] { return launch_z_r2c<T>(static_cast<const T*>(s_in), W, g, p->az, twz, p->tune, s, e); }),
          "z_r2c launch");
   const int total = g.batch * g.nzh, cp = chunk_planes(p);
   for (int pl0 = 0; pl0 < total; pl0 += cp) {
@@ -461,17 +464,50 @@ eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_remove
     EQ_HIP(timed(p, P_Y_INV, [&] { return launch_y<T>(W, g, pl0, npl, 6, p->ay, twy, true, p->tune, s); }, frac),
            "y_inv launch");
   }
+  const size_t Mo = e.on ? (size_t)g.nz * e.ny0 * e.nx0 : M;      // voxels of one output component
   EQ_HIP(timed(p, P_Z_C2R, [&] {
-           return launch_z_c2r<T>(W, static_cast<T*>(s_eq), 6 * M, M, static_cast<const T*>(s_in),
-                                  static_cast<T*>(s_removed), 6, g, p->az, twz, p->tune, s);
+           return launch_z_c2r<T>(W, static_cast<T*>(s_eq), 6 * Mo, Mo, static_cast<const T*>(s_in),
+                                  static_cast<T*>(s_removed), 6, g, p->az, twz, p->tune, s, e);
          }),
          "z_c2r launch");
   return EQ_OK;
 }
 
+// Potential of the removed part: forward transform of the six components, the per-frequency
+// potential (three components) in the x pass, inverse transform of those three into y_out.
 template <typename T>
-eq_status run_check_finite(eq_plan_s* p, const void* s_in) {
-  const size_t n = (size_t)p->g.batch * 6 * field_elems(p);
+eq_status run_potential(eq_plan_s* p, const void* s_in, void* y_out) {
+  using C = cplx<T>;
+  const Geom& g = p->g;
+  hipStream_t st = p->stream;
+  const size_t M = field_elems(p);
+  C* W = static_cast<C*>(p->W);
+  const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
+  const C* twx = tw;
+  const C* twy = tw + g.nx;
+  const C* twz = tw + g.nx + g.ny;
+  const int total = g.batch * g.nzh;
+  EQ_HIP(timed(p, P_Z_R2C, [&] { return launch_z_r2c<T>(static_cast<const T*>(s_in), W, g, p->az, twz, p->tune, st); }),
+         "z_r2c launch");
+  EQ_HIP(timed(p, P_Y_FWD, [&] { return launch_y<T>(W, g, 0, total, 6, p->ay, twy, false, p->tune, st); }),
+         "y_fwd launch");
+  EQ_HIP(timed(p, P_X_POT, [&] {
+           return launch_x<T>(W, g, 0, total, XM_FWD | XM_DISP | XM_INV, p->ax, twx, sym_unit(p), p->tune, st,
+                              p->desc.h);
+         }),
+         "x_pot launch");
+  EQ_HIP(timed(p, P_Y_INV3, [&] { return launch_y<T>(W, g, 0, total, 3, p->ay, twy, true, p->tune, st); }),
+         "y_inv3 launch");
+  EQ_HIP(timed(p, P_Z_C2R3, [&] {
+           return launch_z_c2r<T>(W, static_cast<T*>(y_out), 3 * M, M, nullptr, nullptr, 3, g, p->az, twz, p->tune, st);
+         }),
+         "z_c2r3 launch");
+  return EQ_OK;
+}
+
+template <typename T>
+eq_status run_check_finite(eq_plan_s* p, const void* s_in, size_t n_override = 0) {
+  const size_t n = n_override ? n_override : (size_t)p->g.batch * 6 * field_elems(p);
   EQ_HIP(launch_fill_int(p->flag, 1, 0, p->stream), "fill launch");
   EQ_HIP(timed(p, P_CHECK, [&] { return launch_check_finite<T>(static_cast<const T*>(s_in), n, p->flag, p->stream); }),
          "check_finite launch");
@@ -700,6 +736,29 @@ eq_status eq_project(eq_plan_t p, const void* s_in, void* s_eq, void* s_removed)
   return EQ_OK;
 }
 
+eq_status eq_project_embedded(eq_plan_t p, const eq_embed* em, const void* s_in, void* s_eq, void* s_removed) {
+  if (!p || !em) return fail(EQ_ERR_ARG, "null plan or embedding");
+  if (!s_in || !s_eq) return fail(EQ_ERR_ARG, "null input or output pointer");
+  const Geom& g = p->g;
+  if (em->nx0 < 1 || em->ny0 < 1 || em->ox < 0 || em->oy < 0 || em->ox + em->nx0 > g.nx || em->oy + em->ny0 > g.ny)
+    return fail(EQ_ERR_ARG, "the sample (nx0, ny0) at (ox, oy) must lie inside the plan's (nx, ny)");
+  Embed e;
+  e.nx0 = em->nx0; e.ny0 = em->ny0; e.ox = em->ox; e.oy = em->oy; e.on = true;
+  const size_t n = (size_t)g.batch * 6 * g.nz * e.ny0 * e.nx0;
+  const size_t bytes = n * elem_size(&p->desc);
+  if (s_removed && (ranges_overlap(s_removed, s_in, bytes) || ranges_overlap(s_removed, s_eq, bytes)))
+    return fail(EQ_ERR_ARG, "s_removed overlaps s_in or s_eq");
+  if (s_eq != s_in && ranges_overlap(s_eq, s_in, bytes)) return fail(EQ_ERR_ARG, "s_eq partially overlaps s_in");
+  DeviceGuard dg(p->device);
+  const bool fp64 = p->desc.prec == EQ_FP64;
+  p->last_removed = s_removed != nullptr;
+  if (p->desc.flags & EQ_F_CHECK_FINITE) {
+    eq_status st = fp64 ? run_check_finite<double>(p, s_in, n) : run_check_finite<float>(p, s_in, n);
+    if (st != EQ_OK) return st;
+  }
+  return fp64 ? run_project<double>(p, s_in, s_eq, s_removed, e) : run_project<float>(p, s_in, s_eq, s_removed, e);
+}
+
 eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_out) {
   if (!p) return fail(EQ_ERR_ARG, "null plan");
   if (!s || !norms_host) return fail(EQ_ERR_ARG, "null field or norms pointer");
@@ -709,6 +768,22 @@ eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_
   DeviceGuard dg(p->device);
   return p->desc.prec == EQ_FP64 ? run_residual<double>(p, s, norms_host, div_out)
                                  : run_residual<float>(p, s, norms_host, div_out);
+}
+
+eq_status eq_potential(eq_plan_t p, const void* s_in, void* y_out) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  if (!s_in || !y_out) return fail(EQ_ERR_ARG, "null field or output pointer");
+  const size_t es = elem_size(&p->desc);
+  const size_t M = field_elems(p);
+  const size_t in_bytes = (size_t)p->g.batch * 6 * M * es, out_bytes = (size_t)p->g.batch * 3 * M * es;
+  const uintptr_t x = (uintptr_t)s_in, y = (uintptr_t)y_out;
+  if (y < x + in_bytes && x < y + out_bytes) return fail(EQ_ERR_ARG, "y_out overlaps the field");
+  DeviceGuard dg(p->device);
+  if (p->desc.flags & EQ_F_CHECK_FINITE) {
+    const eq_status st = p->desc.prec == EQ_FP64 ? run_check_finite<double>(p, s_in) : run_check_finite<float>(p, s_in);
+    if (st != EQ_OK) return st;
+  }
+  return p->desc.prec == EQ_FP64 ? run_potential<double>(p, s_in, y_out) : run_potential<float>(p, s_in, y_out);
 }
 
 eq_status eq_plan_tune(eq_plan_t p, const eq_tune* tv) {

@@ -34,12 +34,22 @@ struct Tune {
   int tc_zp = 0;     // columns per workgroup of the three-pass z projection
 };
 
+// Lateral embedding of a sample in the periodic box (the zero-stress buffer of Sections 3.3
+// and 6): the real field that the z passes read and write is (.., nz, ny0, nx0), placed at
+// (ox, oy) in the (ny, nx) plane of the box.  Box voxels outside the sample read as zero and
+// are not written.  on = false: the real field is the whole box.
+struct Embed {
+  int nx0 = 0, ny0 = 0, ox = 0, oy = 0;
+  bool on = false;
+};
+
 // Modes of the fused x pass.
 enum XMode : int {
   XM_FWD = 1,        // forward DFT along x
   XM_PROJ = 2,       // per-frequency projection P A P
   XM_INV = 4,        // inverse DFT along x
   XM_DIV = 8,        // per-frequency divergence i s_j A_ij -> components 0..2
+  XM_DISP = 16,      // per-frequency potential of the removed part -> components 0..2
 };
 
 // Symbol table layout: sym[0 .. nx) x-axis, sym[nx .. nx+ny) y, sym[nx+ny .. +nz) z.
@@ -50,22 +60,24 @@ hipError_t launch_tables(const Geom& g, int op, double h, double* sym, double2* 
 
 template <typename T>
 hipError_t launch_z_r2c(const T* in, cplx<T>* W, const Geom& g, const AxisFft& az, const cplx<T>* tw_z,
-                        const Tune& tn, hipStream_t s);
+                        const Tune& tn, hipStream_t s, const Embed& e = Embed{});
 
 template <typename T>
 hipError_t launch_y(cplx<T>* W, const Geom& g, int pl0, int npl, int ncomp, const AxisFft& ay, const cplx<T>* tw_y,
                     bool inv, const Tune& tn, hipStream_t s);
 
+// h: voxel spacing, used by XM_DISP only (its symbols are h-free)
 template <typename T>
 hipError_t launch_x(cplx<T>* W, const Geom& g, int pl0, int npl, int mode, const AxisFft& ax, const cplx<T>* tw_x,
-                    const double* sym, const Tune& tn, hipStream_t s);
+                    const double* sym, const Tune& tn, hipStream_t s, double h = 1.0);
 
-// out(b, c, z, y, x) = out + b * out_field + c * out_comp + (z * ny + y) * nx + x for c < ncomp.
+// out(b, c, z, y, x) = out + b * out_field + c * out_comp + (z * ny + y) * nx + x for c < ncomp
+// (with an embedding: sample coordinates, (z * ny0 + y - oy) * nx0 + x - ox, sample voxels only).
 // removed (nullable) = in - out at the same offsets.
 template <typename T>
 hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_comp, const T* in, T* removed,
                         int ncomp, const Geom& g, const AxisFft& az, const cplx<T>* tw_z, const Tune& tn,
-                        hipStream_t s);
+                        hipStream_t s, const Embed& e = Embed{});
 
 // Reduction record per field (kRedWidth doubles):
 //   [0] sum_x |r|^2, [1] max_x |r|^2, [2..7] sum_x S_c, [8..13] sum_x S_c^2

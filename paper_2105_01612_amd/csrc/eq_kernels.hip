@@ -82,7 +82,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_z_r2c_g(const T* __restrict__ i
   const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx;
   for (int u = threadIdx.x; u < nz * np; u += blockDim.x) {
     const int z = u / np, j = u - z * np;
-    lds[u] = *reinterpret_cast<const C*>(src + (size_t)z * plane + 2 * j);
+    if (!a.e.on) {
+      lds[u] = *reinterpret_cast<const C*>(src + (size_t)z * plane + 2 * j);
+    } else {
+      const EmbedPair ep = embed_pair(a.e, y, xt * a.tx + 2 * j);
+      const T* s = in + (size_t)bc * nz * ep.plane + (size_t)z * ep.plane;
+      lds[u] = mk<T>(ep.ok0 ? s[ep.off0] : (T)0, ep.ok1 ? s[ep.off1] : (T)0);
+    }
   }
   __syncthreads();
   fft_lines<T, E, false>(lds, np, 1, np, d, tw, threadIdx.x);
@@ -129,6 +135,20 @@ __global__ __launch_bounds__(kMaxThreads) void k_z_c2r_g(const cplx<T>* __restri
   for (int u = threadIdx.x; u < nz * np; u += blockDim.x) {
     const int z = u / np, j = u - z * np;
     const C Z = lds[u];
+    if (a.e.on) {
+      const EmbedPair ep = embed_pair(a.e, y, xt * a.tx + 2 * j);
+      const size_t o = (size_t)b * a.out_field + (size_t)c * a.out_comp + (size_t)z * ep.plane;
+      const T o0 = Z.x * scale, o1 = Z.y * scale;
+      if (ep.ok0) {
+        if (removed) removed[o + ep.off0] = in[o + ep.off0] - o0;
+        out[o + ep.off0] = o0;
+      }
+      if (ep.ok1) {
+        if (removed) removed[o + ep.off1] = in[o + ep.off1] - o1;
+        out[o + ep.off1] = o1;
+      }
+      continue;
+    }
     const size_t off = obase + (size_t)z * plane + 2 * j;
     C o = mk<T>(Z.x * scale, Z.y * scale);
     if (removed) {
@@ -168,7 +188,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_x_g(cplx<T>* __restrict__ W, XA
   const int nx = a.nx, ls = nx + 1, rw = a.rw;
   const int row0 = blockIdx.x * rw;
   const int nrows = min(rw, a.rows - row0);
-  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  const int ncomp_out = (a.mode & (XM_DIV | XM_DISP)) ? 3 : 6;
   int kz, ky;
   for (int c = 0; c < 6; ++c) {
     for (int u = threadIdx.x; u < rw * nx; u += blockDim.x) {
@@ -180,7 +200,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_x_g(cplx<T>* __restrict__ W, XA
   }
   __syncthreads();
   if (a.mode & XM_FWD) fft_lines<T, E, false>(lds, 6 * rw, ls, 1, d, tw, threadIdx.x);
-  if (a.mode & (XM_PROJ | XM_DIV)) {
+  if (a.mode & (XM_PROJ | XM_DIV | XM_DISP)) {
     const double* symx = sym;
     const double* symy = sym + nx;
     const double* symz = sym + nx + a.ny;
@@ -195,7 +215,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_x_g(cplx<T>* __restrict__ W, XA
 #pragma unroll
         for (int c = 0; c < 6; ++c) lds[(c * rw + r) * ls + kx] = A[c];
       } else {
-        divergence_one<T>(A, symx[kx], symy[ky], symz[kz]);
+        vector_op<T>(a.mode, A, symx[kx], symy[ky], symz[kz], a.h);
 #pragma unroll
         for (int c = 0; c < 3; ++c) lds[(c * rw + r) * ls + kx] = A[c];
       }
@@ -547,10 +567,10 @@ FastArgs<T> fast_args(KernelKind kind, const AxisFft& ax, dim3 grid, dim3 block,
 
 template <typename T>
 hipError_t launch_z_r2c(const T* in, cplx<T>* W, const Geom& g, const AxisFft& az, const cplx<T>* tw_z,
-                        const Tune& tn, hipStream_t s) {
+                        const Tune& tn, hipStream_t s, const Embed& e) {
   const int eb = (int)csize<T>();
   const int tx = pick_tx_z(g, az, eb, tn);
-  ZArgs a{g.nx, g.ny, g.nz, tx};
+  ZArgs a{g.nx, g.ny, g.nz, tx, e};
   const size_t lds = lds_z(g, az, eb, tn);
   const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.ny * g.batch * 6));
   const int P = g.nz / az.E;
@@ -591,11 +611,11 @@ hipError_t launch_y(cplx<T>* W, const Geom& g, int pl0, int npl, int ncomp, cons
 
 template <typename T>
 hipError_t launch_x(cplx<T>* W, const Geom& g, int pl0, int npl, int mode, const AxisFft& ax, const cplx<T>* tw_x,
-                    const double* sym, const Tune& tn, hipStream_t s) {
+                    const double* sym, const Tune& tn, hipStream_t s, double h) {
   const int eb = (int)csize<T>();
   const int rw = pick_rw_x(g, ax, eb, tn);
   const int rows = npl * g.ny;
-  XArgs a{g.nx, g.ny, g.nzh, pl0, rows, rw, mode};
+  XArgs a{g.nx, g.ny, g.nzh, pl0, rows, rw, mode, h};
   const size_t lds = lds_x(g, ax, eb, tn);
   const dim3 grid((unsigned)((rows + rw - 1) / rw));
   const int P = g.nx / ax.E;
@@ -616,10 +636,10 @@ hipError_t launch_x(cplx<T>* W, const Geom& g, int pl0, int npl, int mode, const
 template <typename T>
 hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_comp, const T* in, T* removed,
                         int ncomp, const Geom& g, const AxisFft& az, const cplx<T>* tw_z, const Tune& tn,
-                        hipStream_t s) {
+                        hipStream_t s, const Embed& e) {
   const int eb = (int)csize<T>();
   const int tx = pick_tx_z(g, az, eb, tn);
-  ZcArgs a{g.nx, g.ny, g.nz, tx, ncomp, out_field, out_comp};
+  ZcArgs a{g.nx, g.ny, g.nz, tx, ncomp, out_field, out_comp, e};
   const size_t lds = lds_z(g, az, eb, tn);
   const dim3 grid((unsigned)((size_t)(g.nx / tx) * g.ny * ncomp * g.batch));
   const T scale = (T)(1.0 / ((double)g.nx * (double)g.ny * (double)g.nz));
@@ -705,13 +725,13 @@ hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s) {
 
 #define EQ_INSTANTIATE(T)                                                                                          \
   template hipError_t launch_z_r2c<T>(const T*, cplx<T>*, const Geom&, const AxisFft&, const cplx<T>*,           \
-                                      const Tune&, hipStream_t);                                                   \
+                                      const Tune&, hipStream_t, const Embed&);                                     \
   template hipError_t launch_y<T>(cplx<T>*, const Geom&, int, int, int, const AxisFft&, const cplx<T>*, bool,     \
                                   const Tune&, hipStream_t);                                                       \
   template hipError_t launch_x<T>(cplx<T>*, const Geom&, int, int, int, const AxisFft&, const cplx<T>*,          \
-                                  const double*, const Tune&, hipStream_t);                                        \
+                                  const double*, const Tune&, hipStream_t, double);                                \
   template hipError_t launch_z_c2r<T>(const cplx<T>*, T*, size_t, size_t, const T*, T*, int, const Geom&,         \
-                                      const AxisFft&, const cplx<T>*, const Tune&, hipStream_t);                   \
+                                      const AxisFft&, const cplx<T>*, const Tune&, hipStream_t, const Embed&);     \
   template hipError_t launch_div_ddo<T>(const T*, T*, double*, int, const Geom&, double, hipStream_t);           \
   template hipError_t launch_div_stats<T>(const T*, size_t, size_t, const T*, double*, int, const Geom&,         \
                                           hipStream_t);                                                            \

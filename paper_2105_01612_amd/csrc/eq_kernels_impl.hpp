@@ -82,16 +82,77 @@ __device__ __forceinline__ void divergence_one(cplx<T>* A, double sx, double sy,
   for (int i = 0; i < 3; ++i) A[i] = r3[i];
 }
 
+// Potential of the removed part at one frequency.  The removed part is the symmetric
+// gradient (grad y + grad y^T)/2 of Section 3.2; with the derivative symbol i s and
+// n = s/|s|, b = A n, c = n.b, it is n b^T + b n^T - c n n^T = A - P A P, whose unique
+// preimage with zero mean is y = i (c n - 2 b) / |s|.  Zero-symbol frequencies give 0.
+// Symbols are h-free (unit spacing); |s| carries 1/h.  Result in slots 0..2.
+template <typename T>
+__device__ __forceinline__ void potential_one(cplx<T>* A, double sx, double sy, double sz, double h) {
+  using C = cplx<T>;
+  const double ss = sx * sx + sy * sy + sz * sz;
+  if (!(ss > 0.0)) {
+    A[0] = A[1] = A[2] = mk<T>((T)0, (T)0);
+    return;
+  }
+  const double inv = rsqrt_fp64(ss);
+  const T n0 = (T)(sx * inv), n1 = (T)(sy * inv), n2 = (T)(sz * inv), w = (T)(h * inv);
+  const C a00 = A[0], a11 = A[1], a22 = A[2], a12 = A[3], a02 = A[4], a01 = A[5];
+  C b0, b1, b2;
+  b0.x = a00.x * n0 + a01.x * n1 + a02.x * n2;  b0.y = a00.y * n0 + a01.y * n1 + a02.y * n2;
+  b1.x = a01.x * n0 + a11.x * n1 + a12.x * n2;  b1.y = a01.y * n0 + a11.y * n1 + a12.y * n2;
+  b2.x = a02.x * n0 + a12.x * n1 + a22.x * n2;  b2.y = a02.y * n0 + a12.y * n1 + a22.y * n2;
+  C cc;
+  cc.x = n0 * b0.x + n1 * b1.x + n2 * b2.x;
+  cc.y = n0 * b0.y + n1 * b1.y + n2 * b2.y;
+  // i (c n_k - 2 b_k) w  =  (-(c.y n_k - 2 b_k.y) w, (c.x n_k - 2 b_k.x) w)
+  auto pot = [&](T nk, C bk) -> C {
+    return mk<T>(-(cc.y * nk - (T)2 * bk.y) * w, (cc.x * nk - (T)2 * bk.x) * w);
+  };
+  A[0] = pot(n0, b0);
+  A[1] = pot(n1, b1);
+  A[2] = pot(n2, b2);
+}
+
+// The three-output per-frequency operations of the x pass.
+template <typename T>
+__device__ __forceinline__ void vector_op(int mode, cplx<T>* A, double sx, double sy, double sz, double h) {
+  if (mode & XM_DISP) potential_one<T>(A, sx, sy, sz, h);
+  else divergence_one<T>(A, sx, sy, sz);
+}
+
 // ------------------------------------------------------------ arguments ----
 
 struct ZArgs {
   int nx, ny, nz, tx;      // tx: real x-columns per workgroup (even)
+  Embed e;
 };
 
 struct ZcArgs {
   int nx, ny, nz, tx, ncomp;
   size_t out_field, out_comp;
+  Embed e;
 };
+
+// Real column pair (x0, x0 + 1) of box row y inside an embedded sample: the element
+// offsets of (z = 0, y - oy, x - ox) in the sample field, valid where ok0 / ok1.
+struct EmbedPair {
+  size_t off0, off1;
+  size_t plane;      // ny0 * nx0
+  bool ok0, ok1;
+};
+__device__ __forceinline__ EmbedPair embed_pair(const Embed& e, int y, int x0) {
+  EmbedPair r;
+  const int ys = y - e.oy, xs = x0 - e.ox;
+  const bool row = ys >= 0 && ys < e.ny0;
+  r.ok0 = row && xs >= 0 && xs < e.nx0;
+  r.ok1 = row && xs + 1 >= 0 && xs + 1 < e.nx0;
+  r.plane = (size_t)e.ny0 * e.nx0;
+  const size_t base = row ? (size_t)ys * e.nx0 : 0;
+  r.off0 = r.ok0 ? base + xs : 0;
+  r.off1 = r.ok1 ? base + xs + 1 : 0;
+  return r;
+}
 
 struct YArgs {
   int nx, ny, nzh, ncomp, tx, pl0, npl;
@@ -99,6 +160,7 @@ struct YArgs {
 
 struct XArgs {
   int nx, ny, nzh, pl0, rows, rw, mode;   // rows = planes in range * ny
+  double h;                               // voxel spacing (potential mode)
 };
 
 __device__ __forceinline__ size_t y_tile_base(const YArgs& a) {
@@ -138,10 +200,21 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_z_r2c_r(const T* __restrict
   const int nz = F::len(d), nzh = nz / 2 + 1, P = nz / E;
   const int line = threadIdx.x % np, p = threadIdx.x / np;
   const size_t plane = (size_t)a.ny * a.nx;
-  const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx + 2 * line;
   C v[1][E];
+  if (!a.e.on) {
+    const T* src = in + (size_t)bc * nz * plane + (size_t)y * a.nx + (size_t)xt * a.tx + 2 * line;
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[0][i] = *reinterpret_cast<const C*>(src + (size_t)(p + i * P) * plane);
+    for (int i = 0; i < E; ++i) v[0][i] = *reinterpret_cast<const C*>(src + (size_t)(p + i * P) * plane);
+  } else {
+    // embedded sample: columns outside it are the zero-stress buffer
+    const EmbedPair ep = embed_pair(a.e, y, xt * a.tx + 2 * line);
+    const T* src = in + (size_t)bc * nz * ep.plane;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const size_t o = (size_t)(p + i * P) * ep.plane;
+      v[0][i] = mk<T>(ep.ok0 ? src[o + ep.off0] : (T)0, ep.ok1 ? src[o + ep.off1] : (T)0);
+    }
+  }
   const LdsMap m{1, np, 0};
   F::template run<T, 1, false, true, false>(v, lds, m, line, 0, p, d, tw);
   // separate the two packed columns: A = (Z + conj Zm) / 2, B = (Z - conj Zm) / 2i;
@@ -215,6 +288,25 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_z_c2r_r(const cplx<T>* __re
   C v[1][E];
   const LdsMap m{1, np, 0};
   F::template run<T, 1, true, false, true>(v, lds, m, line, 0, p, d, tw);
+  if (a.e.on) {
+    // embedded sample: write its voxels only, in sample coordinates
+    const EmbedPair ep = embed_pair(a.e, y, xt * a.tx + 2 * line);
+    const size_t sbase = (size_t)b * a.out_field + (size_t)c * a.out_comp;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const size_t o = sbase + (size_t)(p + i * P) * ep.plane;
+      const T o0 = v[0][i].x * scale, o1 = v[0][i].y * scale;
+      if (ep.ok0) {
+        if (removed) removed[o + ep.off0] = in[o + ep.off0] - o0;
+        out[o + ep.off0] = o0;
+      }
+      if (ep.ok1) {
+        if (removed) removed[o + ep.off1] = in[o + ep.off1] - o1;
+        out[o + ep.off1] = o1;
+      }
+    }
+    return;
+  }
   const size_t obase = (size_t)b * a.out_field + (size_t)c * a.out_comp + (size_t)y * a.nx + (size_t)xt * a.tx +
                        2 * line;
   if (removed) {
@@ -283,7 +375,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W
   const int row0 = blockIdx.x * rw;
   const int nrows = min(rw, a.rows - row0);
   const bool valid = r < nrows;
-  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  const int ncomp_out = (a.mode & (XM_DIV | XM_DISP)) ? 3 : 6;
   const bool active = c < ncomp_out;
   int kz, ky;
   const size_t base = valid ? x_row_base(a, row0 + r, c, kz, ky) + p : 0;
@@ -298,7 +390,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W
     for (int i = 0; i < E; ++i) lds[m.at(line, p + i * P)] = v[0][i];
     __syncthreads();
   }
-  if (a.mode & (XM_PROJ | XM_DIV)) {
+  if (a.mode & (XM_PROJ | XM_DIV | XM_DISP)) {
     const double* symx = sym;
     const double* symy = sym + nx;
     const double* symz = sym + nx + a.ny;
@@ -316,7 +408,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W
 #pragma unroll
           for (int cc = 0; cc < 6; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
         } else {
-          divergence_one<T>(A, symx[kx], sy, sz);
+          vector_op<T>(a.mode, A, symx[kx], sy, sz, a.h);
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) lds[m.at(cc * rw + rr, kx)] = A[cc];
         }
@@ -369,7 +461,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ 
     __syncthreads();                                       // the last stage read LDS
     F::template run<T, 3, false, true, true>(v + 3, lds, m, r, rw, p, d, tw);
   }
-  if (a.mode & (XM_PROJ | XM_DIV)) {
+  if (a.mode & (XM_PROJ | XM_DIV | XM_DISP)) {
     const double sy = sym[nx + ky], sz = sym[nx + a.ny + kz];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -378,7 +470,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ 
 #pragma unroll
       for (int c = 0; c < 6; ++c) A[c] = v[c][i];
       if (a.mode & XM_PROJ) project_one<T>(A, sym[kx], sy, sz);
-      else divergence_one<T>(A, sym[kx], sy, sz);
+      else vector_op<T>(a.mode, A, sym[kx], sy, sz, a.h);
 #pragma unroll
       for (int c = 0; c < 6; ++c) v[c][i] = A[c];
     }
@@ -389,7 +481,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ 
     __syncthreads();
     F::template run<T, 3, true, true, true>(v + 3, lds, m, r, rw, p, d, tw);
   }
-  const int ncomp_out = (a.mode & XM_DIV) ? 3 : 6;
+  const int ncomp_out = (a.mode & (XM_DIV | XM_DISP)) ? 3 : 6;
   if (valid) {
 #pragma unroll
     for (int c = 0; c < 6; ++c)

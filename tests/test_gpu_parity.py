@@ -264,6 +264,96 @@ def test_invariants_on_gpu_output(prec):
         plan.destroy()
 
 
+# -------------------------------------------------------- zero-stress buffer ---
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("case", [
+    ((16, 24, 20), (13, 17), (3, 4)),     # odd sample, interior
+    ((16, 24, 20), (20, 11), (0, 13)),    # full width, flush with the top edge
+    ((12, 30, 36), (25, 1), (11, 0)),     # one row
+    ((64, 64, 64), (40, 48), (12, 8)),    # a grid the three-pass schedule would otherwise take
+])
+def test_project_embedded_parity(op, prec, case):
+    eq = eqmod()
+    torch = torch_mod()
+    (nz, ny, nx), (nx0, ny0), (ox, oy) = case
+    say("embedded", op, prec, case)
+    S = wl.voronoi_field(wl.FieldSpec((nz, ny0, nx0), grains=8, sigma_grain=60.0, sigma_noise=4.0, seed=nx0 + ny0))
+    plan = eq.plan(nx, ny, nz, op=op, prec=prec, h=0.9)
+    x = to_dev(S, prec)
+    rem = torch.empty_like(x)
+    y = plan.project_embedded(x, nx0, ny0, ox, oy, s_removed=rem)
+    torch.cuda.synchronize()
+    ref, ref_rem = O.project_embedded(upcast(S, prec), (nx, ny), (ox, oy), op, 0.9)
+    got = y.double().cpu().numpy()
+    assert rel_l2(got, ref) <= TOL[prec]
+    assert rel_l2(rem.double().cpu().numpy(), ref_rem) <= (1e-11 if prec == "fp64" else 3e-5)
+    # in place gives the same bits
+    z = x.clone()
+    plan.project_embedded(z, nx0, ny0, ox, oy, s_eq=z)
+    torch.cuda.synchronize()
+    assert torch.equal(z, y)
+    plan.destroy()
+
+
+def test_project_embedded_rejects_bad_geometry():
+    eq = eqmod()
+    torch = torch_mod()
+    plan = eq.plan(16, op="ddo", prec="fp32")
+    x = torch.zeros((6, 16, 8, 8), dtype=torch.float32, device="cuda")
+    for nx0, ny0, ox, oy in ((8, 8, 9, 0), (8, 8, 0, -1), (8, 8, 0, 9)):
+        with pytest.raises(eq.EqError) as ei:
+            plan.project_embedded(x, nx0, ny0, ox, oy)
+        assert ei.value.code == "EQ_ERR_ARG"
+    plan.destroy()
+
+
+# ------------------------------------------- potential of the removed part ---
+
+@pytest.mark.parametrize("shape", [(16, 24, 20), (6, 10, 4), (32, 32, 32)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+def test_potential_parity(op, prec, shape):
+    """eq_potential vs the oracle's least-squares potential; and the GPU's own removed
+    part equals the symmetric gradient of the GPU potential."""
+    eq = eqmod()
+    torch = torch_mod()
+    say("potential", op, prec, shape)
+    h = 0.6
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=10, sigma_grain=50.0, sigma_noise=3.0, sigma_grad=1.0,
+                                      seed=13 + sum(shape)))
+    Su = upcast(S, prec)
+    nz, ny, nx = shape
+    plan = eq.plan(nx, ny, nz, op=op, prec=prec, h=h)
+    x = to_dev(S, prec)
+    y = plan.potential(x)
+    out = torch.empty_like(x)
+    rem = torch.empty_like(x)
+    plan.project(x, out, rem)
+    torch.cuda.synchronize()
+    Y = y.double().cpu().numpy()
+    ref = O.removed_potential(Su, op, h)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    err = float(np.linalg.norm(Y - ref) / np.linalg.norm(ref))
+    say("  rel-L2", err)
+    assert err <= tol
+    sg = O.sym_grad_central_difference(Y, h) if op == "ddo" else O.sym_grad(Y, op, h)
+    assert rel_l2(sg, rem.double().cpu().numpy()) <= (1e-11 if prec == "fp64" else 5e-5)
+    plan.destroy()
+
+
+def test_potential_rejects_overlap():
+    eq = eqmod()
+    torch = torch_mod()
+    plan = eq.plan(8, op="ddo", prec="fp64")
+    x = torch.zeros((6, 8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(eq.EqError) as ei:
+        plan.potential(x, x[:3])
+    assert ei.value.code == "EQ_ERR_ARG"
+    plan.destroy()
+
+
 # -------------------------------------------------------------- residual ----
 
 @pytest.mark.parametrize("shape", [(16, 24, 20), (6, 10, 4), (40, 32, 96), (8, 120, 72)])

@@ -402,7 +402,93 @@ def test_residual_norms_definitions():
         assert O.residual_norms(Seq, op, 1.0)[2] <= 1e-14
 
 
+# ------------------------------------------- potential of the removed part ---
+# Section 3.2: S_exp = S_equil + (grad y + grad y^T)/2.  The oracle's y is a least-squares
+# solve per frequency; the pins check it against that definition in real space.
+
+def _sym_grad_of(op, y, h):
+    return O.sym_grad_central_difference(y, h) if op == "ddo" else O.sym_grad(y, op, h)
+
+
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 10, 4), (8, 6, 12)])
+def test_potential_symmetric_gradient_is_removed_part(op, shape):
+    """sym grad y (DDO: real-space central differences, no transform) equals S - project(S);
+    y has zero mean."""
+    h = 0.7
+    S = random_field(shape, seed=31, scale=40.0) + 10.0
+    y = O.removed_potential(S, op, h)
+    _, removed = O.project(S, op, h)
+    assert rel(_sym_grad_of(op, y, h), removed) <= 1e-12
+    assert np.abs(y.mean(axis=(1, 2, 3))).max() <= 1e-12 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+def test_potential_recovers_a_known_symmetric_gradient(op):
+    """S = c0 + sym grad a + (an equilibrated field) gives y = a exactly, for a with zero
+    mean and no zero-symbol modes (those are invisible to any symmetric gradient)."""
+    shape = (8, 6, 10)
+    h = 1.3
+    rng = np.random.default_rng(9)
+    A = O.dft3(rng.standard_normal((3,) + shape))
+    s = np.stack(np.broadcast_arrays(*[O.axis_symbol(op, n, h)[sl] for n, sl in
+                                       zip(shape[::-1], (np.s_[None, None, : shape[2] // 2 + 1],
+                                                         np.s_[None, :, None], np.s_[:, None, None]))]))
+    A = np.where(np.sum(s * s, axis=0) > 0, A, 0.0)
+    a = O.idft3(A, shape)
+    E, _ = O.project(random_field(shape, seed=10, scale=30.0), op, h)
+    S = _sym_grad_of(op, a, h) + E + np.array([2.0, -1.0, 0.5, 0.3, 0.0, 1.0])[:, None, None, None]
+    y = O.removed_potential(S, op, h)
+    assert rel(y, a) <= 1e-12
+
+
+# ------------------------------------------------------ zero-stress buffer ---
+
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+def test_buffered_box_is_equilibrated_and_sample_cropped(op):
+    """The buffered box's projection is divergence-free over the whole box (the buffer
+    included); the embedded result is its restriction to the sample; a sample that fills
+    the box is the plain periodic projection."""
+    h = 0.8
+    S = random_field((8, 5, 7), seed=21, scale=30.0) + 5.0
+    box, off = (12, 10), (3, 2)
+    B = O.embed_in_buffer(S, box, off)
+    assert np.all(B[:, :, :2] == 0) and np.all(B[:, :, :, 10:] == 0) and np.array_equal(B[:, :, 2:7, 3:10], S)
+    Beq, _ = O.project(B, op, h)
+    r = O.divergence_central_difference(Beq, h) if op == "ddo" else O.divergence(Beq, op, h)
+    assert np.abs(r).max() <= 1e-12 * np.abs(B).max()
+    got, rem = O.project_embedded(S, box, off, op, h)
+    assert np.array_equal(got, Beq[:, :, 2:7, 3:10]) and np.allclose(rem, S - got, rtol=0, atol=1e-12)
+    full = random_field((6, 8, 10), seed=22, scale=30.0)
+    a, _ = O.project_embedded(full, (10, 8), (0, 0), op, h)
+    b, _ = O.project(full, op, h)
+    assert np.array_equal(a, b)
+
+
 # ------------------------------------------------------- planted mistakes ---
+
+def _potential_pin_fails(op="ddo", shape=(6, 8, 4)):
+    S = random_field(shape, seed=12, scale=40.0)
+    y = O.removed_potential(S, op, 0.8)
+    _, removed = O.project(S, op, 0.8)
+    return rel(_sym_grad_of(op, y, 0.8), removed) > 1e-6
+
+
+def test_planted_potential_missing_rank_one_term_is_caught(monkeypatch):
+    def mutant(R, s):
+        rhs = -1j * np.einsum("ij...,j...->i...", R, s)
+        ss = np.sum(s * s, axis=0)
+        return np.where(ss > 0, 2.0 * rhs / np.where(ss > 0, ss, 1.0), 0.0)   # (1/2)|s|^2 I only
+
+    monkeypatch.setattr(O.equilibrium, "potential_spectrum", mutant)
+    assert _potential_pin_fails("ddo") and _potential_pin_fails("cdo")
+
+
+def test_planted_potential_conjugate_is_caught(monkeypatch):
+    orig = O.equilibrium.potential_spectrum
+    monkeypatch.setattr(O.equilibrium, "potential_spectrum", lambda R, s: np.conj(orig(R, s)))
+    assert _potential_pin_fails("ddo")
+
 
 def _argmin_fails(monkeypatch_ctx, op, shape=(4, 6, 8)):
     S = random_field(shape, seed=5, scale=50.0) + 20.0
