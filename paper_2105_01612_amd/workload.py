@@ -29,7 +29,8 @@ from typing import Optional, Sequence, Tuple
 
 import numpy as np
 
-__all__ = ["FieldSpec", "voronoi_field", "CONFIG_SPECS", "config_field", "plane_shape"]
+__all__ = ["FieldSpec", "voronoi_field", "CONFIG_SPECS", "config_field", "plane_shape", "grain_labels",
+           "grain_average"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -95,6 +96,29 @@ def voronoi_field(spec: FieldSpec, dtype=np.float64, chunk_planes: Optional[int]
     if spec.sigma_noise > 0:
         for c in range(6):
             out[c] += rng.normal(0.0, spec.sigma_noise, size=(nz, ny, nx)).astype(dtype, copy=False)
+    return out
+
+
+def grain_labels(spec: FieldSpec, chunk_planes: Optional[int] = None) -> np.ndarray:
+    """Grain index per voxel (nz, ny, nx) of the field ``voronoi_field(spec)`` (same seeds)."""
+    nz, ny, nx = spec.shape
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    seeds = rng.random((spec.grains, 3))
+    if chunk_planes is None:
+        chunk_planes = max(1, (1 << 22) // (ny * nx))
+    grain, _ = _grain_map(spec.shape, seeds, chunk_planes)
+    return grain
+
+
+def grain_average(S: np.ndarray, labels: np.ndarray, grains: int) -> np.ndarray:
+    """Replace every voxel of each component by the mean of its grain (Section 5.1: the
+    grain-averaged field the filter is applied to).  S: (6, nz, ny, nx)."""
+    lab = labels.ravel()
+    count = np.bincount(lab, minlength=grains).astype(np.float64)
+    out = np.empty_like(S)
+    for c in range(6):
+        mean = np.bincount(lab, weights=S[c].ravel().astype(np.float64), minlength=grains) / np.maximum(count, 1.0)
+        out[c] = mean[labels].astype(S.dtype, copy=False)
     return out
 
 
