@@ -168,13 +168,15 @@ eq_status eq_plan_reset_stats(eq_plan_t p);
  *            3 = three passes (xy plane, z + projection, xy plane), available when
  *            nx == ny in {64, 128, 256} (FP64: 64, 128) and nz in {64, 128, 256};
  *            0 = library default (three passes where available and nx <= 128),
- *   tc_zp    (ky, kx) columns per workgroup of the three-pass z projection (must divide ny).
+ *   tc_zp    (ky, kx) columns per workgroup of the three-pass z projection (must divide ny),
+ *   radix4   1: radix-4 stages on x (FP32, nx a power of two in 32 .. 512: the six-component
+ *            x kernel then holds 6 x 4 values per lane instead of 6 x 8); ignored elsewhere.
  * Invalid shapes for this grid return EQ_ERR_ARG (EQ_ERR_SIZE if LDS would exceed the device
  * limit) and leave the plan unchanged.  Every setting computes the same transform; results
  * may differ only by floating-point rounding order when radix16 changes.
  * The EQ_TUNE environment variable ("tx_y=16,tx_z=32,rw_x=4,chunk=32,radix16=2,schedule=5") seeds the
  * tuning at eq_plan.  eq_plan_get_tune reports the settings in effect (defaults resolved). */
-typedef struct { int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp; } eq_tune;
+typedef struct { int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4; } eq_tune;
 eq_status eq_plan_tune(eq_plan_t p, const eq_tune* t);
 eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t);
 

@@ -6,7 +6,8 @@ passes, the x pass or the three-pass z projection -- so the search is per pass:
 1. five-pass radix schedule: time the plan once with every axis on radix-8 stages
    and once with every axis on radix-16 stages; each axis keeps whichever its own
    passes ran faster with;
-2. five-pass tile shapes: sweep tx_z, tx_y and rw_x, each against its own pass time;
+2. five-pass tile shapes: sweep tx_z, tx_y and rw_x, each against its own pass time, then
+   radix-4 x stages with a few rw_x values against the x pass;
 3. where the grid allows the three-pass schedule: sweep tc_zp against the z
    projection's time, then keep whichever schedule projects faster in total.
 
@@ -109,7 +110,7 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
             mask |= 2
         if _cost(t16, Z_PASSES) < _cost(t8, Z_PASSES):
             mask |= 4
-    best = {"tx_y": 0, "tx_z": 0, "rw_x": 0, "chunk": 0, "radix16": mask, "schedule": 5, "tc_zp": 0}
+    best = {"tx_y": 0, "tx_z": 0, "rw_x": 0, "chunk": 0, "radix16": mask, "schedule": 5, "tc_zp": 0, "radix4": 0}
     base = trial(**best)
     log = {"radix16_all8": t8, "radix16_all16": t16, "default_shapes": base}
 
@@ -127,6 +128,17 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
             if c < best_c:
                 best_v, best_c = v, c
         best[knob] = best_v
+    # radix-4 x stages (fewer registers per lane in the six-component x kernel)
+    best_x = _cost(trial(**best) or {}, X_PASSES) or float("inf")
+    for rw in (0, 1, 2, 4):
+        t = trial(**dict(best, radix4=1, rw_x=rw))
+        if t is None or plan.get_tune()["radix4"] != 1:
+            continue
+        c = _cost(t, X_PASSES)
+        log[f"radix4 rw_x={rw}"] = c
+        if c < best_x:
+            best_x = c
+            best = dict(best, radix4=1, rw_x=rw)
     five = trial(**best)
     cost5 = _cost(five, FIVE_PASSES) if five else float("inf")
     # 3. three-pass schedule, where the grid allows it

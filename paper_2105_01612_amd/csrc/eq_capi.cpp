@@ -51,7 +51,7 @@ bool fault_inject_alloc() {
 // (E = 8) or, with `wide` and n >= 128, 16s (E = 16), with one 2/4/8 to finish; a factor 3 or 5
 // switches to E = 24 or 40 with the power of two in 8s and 4/2.  Edges with both
 // 3 and 5, or fewer than three factors of 2, use the generic engine.
-bool factor_axis(int n, AxisFft* out, bool wide = false) {
+bool factor_axis(int n, AxisFft* out, bool wide = false, bool narrow = false) {
   if (n < 4 || n > 1024 || (n & 1)) return false;
   int m = n, a = 0, b = 0, c = 0;
   while (m % 2 == 0) { m /= 2; ++a; }
@@ -61,6 +61,17 @@ bool factor_axis(int n, AxisFft* out, bool wide = false) {
   FftDesc d{};
   d.n = n;
   int k = 0;
+  if (narrow && b == 0 && c == 0 && a >= 3) {
+    // radix-4 stages (E = 4): a quarter of the registers per lane of radix 16
+    for (int i = 0; i < a / 2; ++i) d.r[k++] = 4;
+    if (a % 2) d.r[k++] = 2;
+    if (k > kMaxStages) return false;
+    d.nst = k;
+    out->d = d;
+    out->E = 4;
+    out->fast = true;
+    return true;
+  }
   if (a >= 3 && !(b > 0 && c > 0)) {
     int E;
     // E = 16 (radix-16 stages) only where asked: the y passes run best with it, the
@@ -388,6 +399,7 @@ Tune tune_from_env() {
       else if (key == "rw_x") t.rw_x = val;
       else if (key == "chunk") t.chunk = val;
       else if (key == "radix16") t.radix16 = val;
+      else if (key == "radix4") t.radix4 = val;
       else if (key == "schedule") t.schedule = val;
       else if (key == "tc_zp") t.tc_zp = val;
     }
@@ -396,10 +408,14 @@ Tune tune_from_env() {
   return t;
 }
 
-// Radix schedules of the three axes for a radix-16 mask (-1: y only).
-void set_axes(eq_plan_s* p, int mask) {
+// Radix schedules of the three axes for a radix-16 mask (-1: y only); radix4 = 1 puts the x
+// axis on radix-4 stages where the six-component x kernel serves it (FP32, powers of two
+// 32 .. 512), and is ignored elsewhere.
+void set_axes(eq_plan_s* p, int mask, int radix4 = 0) {
   if (mask < 0) mask = 2;
-  factor_axis(p->desc.nx, &p->ax, (mask & 1) != 0);
+  const int nx = p->desc.nx;
+  const bool x4 = radix4 == 1 && x6_radix4_available(nx, p->desc.prec == EQ_FP64);
+  factor_axis(nx, &p->ax, (mask & 1) != 0, x4);
   factor_axis(p->desc.ny, &p->ay, (mask & 2) != 0);
   factor_axis(p->desc.nz, &p->az, (mask & 4) != 0);
 }
@@ -640,7 +656,7 @@ eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out) {
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }
   p->tune = tune_from_env();
-  set_axes(p, p->tune.radix16);
+  set_axes(p, p->tune.radix16, p->tune.radix4);
   if ((st = check_shapes(p, p->tune)) != EQ_OK) { release(p); return st; }
   if (d->flags & EQ_F_OWN_STREAM) {
     e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
@@ -790,14 +806,16 @@ eq_status eq_plan_tune(eq_plan_t p, const eq_tune* tv) {
   if (!p || !tv) return fail(EQ_ERR_ARG, "null pointer");
   if (tv->tx_y < 0 || tv->tx_z < 0 || tv->rw_x < 0) return fail(EQ_ERR_ARG, "negative launch shape");
   if (tv->radix16 < -1 || tv->radix16 > 7) return fail(EQ_ERR_ARG, "radix16 must be -1 or a mask of 1|2|4");
+  if (tv->radix4 != 0 && tv->radix4 != 1) return fail(EQ_ERR_ARG, "radix4 must be 0 or 1 (x axis)");
   Tune t;
   t.tx_y = tv->tx_y; t.tx_z = tv->tx_z; t.rw_x = tv->rw_x; t.chunk = tv->chunk;
   t.radix16 = tv->radix16;
+  t.radix4 = tv->radix4;
   t.schedule = tv->schedule;
   t.tc_zp = tv->tc_zp;
   DeviceGuard dg(p->device);
   const AxisFft ax = p->ax, ay = p->ay, az = p->az;
-  set_axes(p, t.radix16);
+  set_axes(p, t.radix16, t.radix4);
   eq_status st = check_shapes(p, t);
   if (st != EQ_OK) {
     p->ax = ax; p->ay = ay; p->az = az;
@@ -817,6 +835,7 @@ eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t) {
   t->rw_x = pick_rw_x(p->g, p->ax, eb, p->tune);
   t->chunk = chunk_planes(p);
   t->radix16 = (p->ax.E == 16 ? 1 : 0) | (p->ay.E == 16 ? 2 : 0) | (p->az.E == 16 ? 4 : 0);
+  t->radix4 = p->ax.E == 4 ? 1 : 0;
   const bool plane = use_plane(p, p->tune);
   t->schedule = plane ? 3 : 5;
   t->tc_zp = plane ? pick_tc_zproj(p->g, p->desc.prec == EQ_FP64, p->tune.tc_zp) : 0;

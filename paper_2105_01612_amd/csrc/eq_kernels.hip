@@ -426,6 +426,7 @@ bool ct_enabled() {
 template <typename T>
 void dispatch_fast(const FastArgs<T>& a) {
   if (ct_enabled() && (ct_launch_pow2<T>(a) || ct_launch_mixed<T>(a))) return;
+  if (a.E == 4) return;   // unreachable: radix-4 plans exist only where the x6 schedules above serve them
   switch (a.E) {
     case 8: launch_with<T, RtFft<8>>(a); break;
     case 16: launch_with<T, RtFft<16>>(a); break;
@@ -452,12 +453,19 @@ template <typename T>
 bool use_x6(const AxisFft& ax) {
   // needs a compile-time radix-8 schedule (the powers of two 32 .. 512, eq_sched_pow2.hip)
   const int n = ax.d.n;
-  if (!ax.fast || ax.E != 8 || n < 32 || n > 512 || (n & (n - 1)) != 0 || !ct_enabled()) return false;
+  if (!ax.fast || (ax.E != 8 && ax.E != 4) || n < 32 || n > 512 || (n & (n - 1)) != 0 || !ct_enabled()) return false;
   const char* e = std::getenv("EQ_X6");
   if (e) return e[0] == '1';
   return sizeof(T) == 4;
 }
 bool use_x6_eb(const AxisFft& ax, int eb) { return eb == 8 ? use_x6<float>(ax) : use_x6<double>(ax); }
+bool x6_radix4_available(int nx, bool fp64) {
+  AxisFft ax{};
+  ax.d.n = nx;
+  ax.E = 4;
+  ax.fast = true;
+  return !fp64 && use_x6<float>(ax);
+}
 // Register-engine shapes aim at ~256 threads per workgroup (several workgroups per
 // CU so load, transform and store phases of different workgroups overlap) with
 // tiles at least 128 bytes wide along x.

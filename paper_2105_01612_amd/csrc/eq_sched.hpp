@@ -24,9 +24,24 @@ bool try_sched(const FastArgs<T>& a) {
   return true;
 }
 
+// radix 4 (E = 4): only the six-component x kernel takes it (FP32; its 6 * E values per lane)
+template <typename T, int... Rs>
+bool try_sched_x6(const FastArgs<T>& a) {
+  using S = Sched<Rs...>;
+  if (a.kind != KK_X6 || a.n != S::N || a.E != S::E || !radices_match<Rs...>(a.d)) return false;
+  hipLaunchKernelGGL((k_x6_r<T, S>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+  return true;
+}
+
 // powers of two: radix 8 (E = 8) and radix 16 (E = 16)
 template <typename T>
 bool ct_launch_pow2_impl(const FastArgs<T>& a) {
+  if (a.E == 4) {
+    if constexpr (sizeof(T) == 4)
+      return try_sched_x6<T, 4, 4, 2>(a) || try_sched_x6<T, 4, 4, 4>(a) || try_sched_x6<T, 4, 4, 4, 2>(a) ||
+             try_sched_x6<T, 4, 4, 4, 4>(a) || try_sched_x6<T, 4, 4, 4, 4, 2>(a);
+    return false;
+  }
   return try_sched<T, 8, 4>(a) || try_sched<T, 8, 8>(a) || try_sched<T, 8, 8, 2>(a) || try_sched<T, 8, 8, 4>(a) ||
          try_sched<T, 8, 8, 8>(a) || try_sched<T, 16, 8>(a) || try_sched<T, 16, 16>(a) || try_sched<T, 16, 16, 2>(a);
 }

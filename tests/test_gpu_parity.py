@@ -203,6 +203,25 @@ def test_three_pass_batch_and_plane_edges(prec):
         assert rel_l2(gotb[b], ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("shape", [(16, 12, 32), (20, 8, 64), (8, 6, 128), (4, 4, 256), (4, 4, 512)])
+def test_radix4_x_parity(op, shape):
+    """FP32 with radix-4 x stages (the six-component x kernel holding 6 x 4 values per lane)."""
+    eq = eqmod()
+    torch = torch_mod()
+    nz, ny, nx = shape
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=6, sigma_grain=80.0, sigma_noise=4.0, seed=nx + 1))
+    plan = eq.plan(nx, ny, nz, op=op, prec="fp32")
+    for rw in (0, 1, 2):
+        plan.tune(schedule=5, radix4=1, rw_x=rw)
+        assert plan.get_tune()["radix4"] == 1
+        x = to_dev(S, "fp32")
+        got = plan.project(x).double().cpu().numpy()
+        ref, _ = O.project(upcast(S, "fp32"), op)
+        assert rel_l2(got, ref) <= TOL["fp32"], rw
+    plan.destroy()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batched_equals_single_and_oracle(prec):
     eq = eqmod()
