@@ -167,11 +167,12 @@ template <bool INV, typename C> struct Dft<5, INV, C> {
 
 // ------------------------------------------------------- register engine --
 
-// LDS placement of element idx of a line: line * ls + idx * es (+ idx / 16 with skew,
-// which breaks the power-of-two strides of Stockham writes on contiguous lines).
+// LDS placement of element idx of a line: line * ls + idx * es (+ idx >> skew, which breaks
+// the power-of-two strides of Stockham writes on contiguous lines).  kSkew is the usual shift.
+constexpr int kSkew = 4;
 struct LdsMap {
-  int ls, es, skew;
-  EQ_HD int at(int line, int idx) const { return line * ls + idx * es + (skew ? (idx >> 4) : 0); }
+  int ls, es, skew;   // skew: one pad element every 2^skew elements (0: none)
+  EQ_HD int at(int line, int idx) const { return line * ls + idx * es + (skew ? (idx >> skew) : 0); }
 };
 
 // j mod Ns; Ns is a power of two except after a radix-3/5 stage (those come last in a schedule).

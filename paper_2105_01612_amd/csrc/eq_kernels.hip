@@ -510,13 +510,13 @@ int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
     // one thread per (row, p); about 64 threads (one wavefront) per workgroup measured best
     int rw = 64 / P;
     if (rw < 1) rw = 1;
-    const int ls = g.nx + g.nx / 16 + 1;
+    const int ls = g.nx + (g.nx >> kX6Skew) + 1;
     while (rw > 1 && (rw * P > kMaxFastThreads || (size_t)3 * rw * ls * eb > kLdsPreferred)) --rw;
     return rw;
   }
   if (ax.fast) {
     // one line per thread group: about 128 threads per workgroup (several rows when lines are short)
-    const int ls = g.nx + g.nx / 16 + 1;
+    const int ls = g.nx + (g.nx >> kSkew) + 1;
     int rw = 128 / (6 * P);
     if (rw < 1) rw = 1;
     while (rw > 1 && (6 * rw * P > kMaxFastThreads || (size_t)6 * rw * ls * eb > kLdsPreferred)) --rw;
@@ -537,8 +537,9 @@ size_t lds_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
   return (size_t)(pick_tx_z(g, az, eb, tn) / 2) * g.nz * eb;
 }
 size_t lds_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
-  const int ls = ax.fast ? g.nx + g.nx / 16 + 1 : g.nx + 1;
-  const int lines = use_x6_eb(ax, eb) ? 3 : 6;     // the six-component kernel transforms three rows at a time
+  const bool six = use_x6_eb(ax, eb);
+  const int ls = !ax.fast ? g.nx + 1 : g.nx + (g.nx >> (six ? kX6Skew : kSkew)) + 1;
+  const int lines = six ? 3 : 6;     // the six-component kernel transforms three rows at a time
   return (size_t)lines * pick_rw_x(g, ax, eb, tn) * ls * eb;
 }
 

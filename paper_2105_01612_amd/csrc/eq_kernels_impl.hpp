@@ -16,6 +16,7 @@ namespace eq {
 constexpr int kMaxThreads = 1024;      // generic-engine workgroups
 constexpr int kMaxFastThreads = 512;   // register-engine workgroups (up to 256 VGPRs per lane)
 constexpr size_t kLdsPreferred = 64 * 1024;
+constexpr int kX6Skew = 4;             // pad shift of the six-component x kernel's LDS lines
 
 // ----------------------------------------------------- per-frequency ops ---
 
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x_r(cplx<T>* __restrict__ W
   C v[1][E];
 #pragma unroll
   for (int i = 0; i < E; ++i) v[0][i] = valid ? W[base + (size_t)i * P] : mk<T>((T)0, (T)0);
-  const LdsMap m{nx + nx / 16 + 1, 1, 1};
+  const LdsMap m{nx + (nx >> kSkew) + 1, 1, kSkew};
   if (a.mode & XM_FWD) {
     F::template run<T, 1, false, true, false>(v, lds, m, line, 0, p, d, tw);
   } else {
@@ -455,7 +456,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ 
   for (int c = 0; c < 6; ++c)
 #pragma unroll
     for (int i = 0; i < E; ++i) v[c][i] = valid ? W[base + c * cstride + (size_t)i * P] : mk<T>((T)0, (T)0);
-  const LdsMap m{nx + nx / 16 + 1, 1, 1};
+  const LdsMap m{nx + (nx >> kX6Skew) + 1, 1, kX6Skew};
   if (a.mode & XM_FWD) {
     F::template run<T, 3, false, true, true>(v, lds, m, r, rw, p, d, tw);
     __syncthreads();                                       // the last stage read LDS

@@ -42,7 +42,7 @@ struct PlaneShape {
   static constexpr int EX = FX::E, PX = NX / EX, LX = NT / PX, RX = (NY / 2) / LX;
   static constexpr int EY = FY::E, PY = NY / EY, LY = NT / PY, RY = (NX / 2) / LY;
   static constexpr int NXH = NX / 2, NJ = NY / 2;          // W2 row length (Nyquist apart)
-  static constexpr int LSX = NX + NX / 16 + 1;       // LDS stride of one x line (skewed)
+  static constexpr int LSX = NX + (NX >> kSkew) + 1;  // LDS stride of one x line (skewed)
   static constexpr int TS = LY + 1;                  // LDS stride of one tile row
   // forward: ZA, ZB (NJ rows each), y exchange (LY columns), column-0 buffer (NY);
   // inverse: tile of NY rows, y exchange.  The x exchange overlaps either.
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* __restrict__ in, cplx
   const int px = tid % PX, lx = tid / PX;
   // ---- x phase: packed line j = lx + r*LX holds rows 2j (real part) and 2j+1 (imaginary part)
   C v[RX][EX];
-  const LdsMap mx{S::LSX, 1, 1};
+  const LdsMap mx{S::LSX, 1, kSkew};
 #pragma unroll
   for (int r = 0; r < RX; ++r) {
     const T* row = src + (size_t)(2 * (lx + r * LX)) * NX + px;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2
     __syncthreads();
   }
   // ---- x phase (inverse): real part -> row 2j, imaginary part -> row 2j+1
-  const LdsMap mx{S::LSX, 1, 1};
+  const LdsMap mx{S::LSX, 1, kSkew};
 #pragma unroll
   for (int r = 0; r < RX; ++r) {
     FX::template run<T, 1, true, true, true>(&v[r], lds, mx, lx, 0, px, dd, twx);
@@ -322,8 +322,8 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__
   for (int c = 0; c < 6; ++c)
 #pragma unroll
     for (int i = 0; i < E; ++i) v[c][i] = buf_load<T>(rs, voff, soff(c, i));
-  constexpr int LS = NZ + NZ / 16 + 1;    // contiguous, skewed column lines: stage offsets fold into immediates
-  const LdsMap m{LS, 1, 1};
+  constexpr int LS = NZ + (NZ >> kSkew) + 1;   // contiguous, skewed column lines: stage offsets fold into immediates
+  const LdsMap m{LS, 1, kSkew};
   C* reg[2] = {lds, lds + (size_t)a.tc * LS};
 #pragma unroll
   for (int c = 0; c < 6; ++c) FZ::template run<T, 1, false, true, true>(&v[c], reg[c & 1], m, col, 0, p, dd, tw);
@@ -415,7 +415,7 @@ hipError_t zproj_n(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double*
   const ZpArgs a{g.nx, g.ny, g.nz, tc, g.batch};
   if ((double)6 * NZ * g.ny * (g.nx / 2) * sizeof(cplx<T>) >= 4294967296.0) return hipErrorInvalidValue;  // 32-bit offsets
   if (tc < 1 || g.ny % tc != 0 || tc * (NZ / F::E) > kMaxFastThreads) return hipErrorInvalidValue;
-  const size_t lds = 2 * (size_t)tc * (NZ + NZ / 16 + 1) * sizeof(cplx<T>);
+  const size_t lds = 2 * (size_t)tc * (NZ + (NZ >> kSkew) + 1) * sizeof(cplx<T>);
   static const hipError_t once = allow_lds(reinterpret_cast<const void*>(&k_zproj<T, F>), 160 * 1024);
   if (once != hipSuccess && lds > 64 * 1024) return once;
   const int ntile = g.ny * (g.nx / 2) / tc + g.ny / tc;
@@ -449,7 +449,9 @@ int pick_tc_zproj(const Geom& g, bool fp64, int want) {
   return tc;
 }
 
-size_t zproj_lds(const Geom& g, bool fp64, int tc) { return 2 * (size_t)tc * (g.nz + g.nz / 16 + 1) * (fp64 ? 16 : 8); }
+size_t zproj_lds(const Geom& g, bool fp64, int tc) {
+  return 2 * (size_t)tc * (g.nz + (g.nz >> kSkew) + 1) * (fp64 ? 16 : 8);
+}
 
 template <typename T>
 hipError_t launch_plane_r2c(const T* in, cplx<T>* W2, const Geom& g, const cplx<T>* twx, const cplx<T>* twy,

@@ -25,7 +25,7 @@ double run_case(const FftDesc& d, bool in_regs, bool out_regs, unsigned seed) {
   srand(seed);
   for (int i = 0; i < n; ++i) x[i] = {rand() / (double)RAND_MAX - 0.5, rand() / (double)RAND_MAX - 0.5};
   // one line, skewed contiguous layout
-  LdsMap m{n + n / 16 + 1, 1, 1};
+  LdsMap m{n + (n >> kSkew) + 1, 1, kSkew};
   std::vector<C> lds(m.ls);
   std::vector<std::vector<C>> v(P, std::vector<C>(E));
   for (int p = 0; p < P; ++p)
