@@ -202,6 +202,15 @@ def run_serve(args):
     lam = 0.7 * sat["requests_per_s"]
     arr = wl.poisson_arrivals(args.requests, lam, seed=4000)
     res = srv.run([Request(i, int(n), float(a), f) for i, (n, a, f) in enumerate(zip(ns, arr, fields))])
+    # admission policies at the same arrivals: in-flight cap and smallest-first
+    policies = {}
+    for order, cap in (("fifo", 4), ("sjf", 4), ("sjf", 8), ("sjf", 16)):
+        srv.order, srv.max_inflight = order, cap
+        r = srv.run([Request(i, int(n), float(a), f) for i, (n, a, f) in enumerate(zip(ns, arr, fields))])
+        policies[f"{order}_cap{cap}"] = {k: r[k] for k in ("requests_per_s", "p50_ms", "p99_ms", "mean_ms", "max_ms")}
+        policies[f"{order}_cap{cap}"]["per_size"] = r["per_size"]
+        log(f"[bench] serve 0.7x {order} cap {cap}: p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms")
+    srv.order, srv.max_inflight = "fifo", None
     over = srv.run([Request(i, int(n), float(a), f) for i, (n, a, f) in
                     enumerate(zip(ns, wl.poisson_arrivals(args.requests, 1.2 * sat["requests_per_s"], 4001), fields))])
     srv.close()
@@ -211,7 +220,8 @@ def run_serve(args):
                                    f"one grain per 16^3 voxels, FP32 {args.op.upper()}, graphs per slot, "
                                    f"budget {args.budget_gb} GiB"},
             "arrival_rate_per_s": lam, "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
-            "saturated": sat, "at_0.7_saturation": res, "at_1.2_saturation": over}
+            "saturated": sat, "at_0.7_saturation": res, "at_1.2_saturation": over,
+            "policies_at_0.7_saturation": policies}
 
 
 def run_grain_avg(args):

@@ -96,10 +96,20 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, backend, budget_bytes: int, max_slots_per_class: int = 8):
+    """max_inflight caps the requests running at once (None: as many as slots allow); with a
+    cap, requests queue on the host and the device runs fewer, shorter-lived streams, which
+    bounds how long a small request shares the GPU with large ones.  order: "fifo" admits in
+    arrival order, "sjf" admits the smallest waiting field first."""
+
+    def __init__(self, backend, budget_bytes: int, max_slots_per_class: int = 8,
+                 max_inflight: Optional[int] = None, order: str = "fifo"):
+        if order not in ("fifo", "sjf"):
+            raise ValueError("order must be 'fifo' or 'sjf'")
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_slots = max_slots_per_class
+        self.max_inflight = max_inflight
+        self.order = order
         self.slots: Dict[int, List[Slot]] = collections.defaultdict(list)
         self.used = 0
         self.peak_used = 0
@@ -189,9 +199,13 @@ class Server:
                     busy.remove(s)
                     finished.append(r)
                     progressed = True
-            # admissions in arrival order; a request that cannot be placed does not block other classes
+            # admissions (arrival order, or smallest first); a request that cannot be placed does not
+            # block other classes
             blocked = set()
-            for r in list(queue):
+            waiting = sorted(queue, key=lambda q: (q.n, q.arrival, q.rid)) if self.order == "sjf" else list(queue)
+            for r in waiting:
+                if self.max_inflight is not None and len(busy) >= self.max_inflight:
+                    break
                 if r.n in blocked:
                     continue
                 s = self._acquire(r.n)

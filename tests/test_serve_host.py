@@ -111,3 +111,32 @@ def test_request_larger_than_budget_is_refused():
     srv = Server(FakeBackend(clock), 100)
     with pytest.raises(ValueError):
         srv.run([Request(0, 64, 0.0)], clock=clock)
+
+
+@pytest.mark.parametrize("order", ["fifo", "sjf"])
+def test_inflight_cap_is_respected(order):
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    srv = Server(be, budget_bytes=10 ** 12, max_inflight=3, order=order)
+    reqs = make_requests(300, 5e4, (16, 24, 32, 48))
+    busy_max = {"n": 0}
+    orig = be.submit
+
+    def submit(h, r):
+        orig(h, r)
+        live = sum(1 for ss in srv.slots.values() for sl in ss if sl.req is not None)
+        busy_max["n"] = max(busy_max["n"], live)
+
+    be.submit = submit
+    res = srv.run(reqs, clock=clock)
+    assert res["completed"] == 300
+    assert busy_max["n"] <= 3
+
+
+def test_sjf_admits_smallest_first():
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    srv = Server(be, budget_bytes=10 ** 12, max_inflight=1, order="sjf")
+    reqs = [Request(0, 48, 0.0), Request(1, 16, 0.0), Request(2, 32, 0.0)]
+    srv.run(reqs, clock=clock)
+    assert [rid for (what, rid, _) in be.log if what == "submit"] == [1, 2, 0]
