@@ -416,6 +416,9 @@ void set_axes(eq_plan_s* p, int mask, int radix4 = 0) {
   const int nx = p->desc.nx;
   const bool x4 = radix4 == 1 && x6_radix4_available(nx, p->desc.prec == EQ_FP64);
   factor_axis(nx, &p->ax, (mask & 1) != 0, x4);
+  // the one-line-per-thread-group x pass needs 6 * nx / E threads in one workgroup: past 512
+  // (nx = 1024 on radix 8) take radix 16
+  if (p->ax.fast && p->ax.E == 8 && 6 * (nx / 8) > 512) factor_axis(nx, &p->ax, true);
   factor_axis(p->desc.ny, &p->ay, (mask & 2) != 0);
   factor_axis(p->desc.nz, &p->az, (mask & 4) != 0);
 }

@@ -223,6 +223,19 @@ def test_radix4_x_parity(op, shape):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("shape", [(4, 6, 1024), (6, 1024, 4), (1024, 4, 6), (4, 6, 960), (1000, 4, 6),
+                                   (6, 768, 4)])
+def test_maximum_edges(prec, op, shape):
+    """Edges at the 1024 limit and 3/5-smooth edges near it, on every axis."""
+    say("max edge", prec, op, shape)
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=5, sigma_grain=50.0, sigma_noise=3.0, seed=sum(shape)))
+    got, rem = run_project(S, op, prec)
+    ref, ref_rem = O.project(upcast(S, prec), op)
+    assert rel_l2(got, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batched_equals_single_and_oracle(prec):
     eq = eqmod()
     torch = torch_mod()
