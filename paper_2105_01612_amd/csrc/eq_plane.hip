@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__
 // radix-8 stages throughout (radix 16 needs more registers than a resident plane leaves)
 template <typename T, int N> struct PlaneCfg;
 template <> struct PlaneCfg<float, 64> { static constexpr int NT = 256; using FX = Sched<8, 8>; using FY = FX; };
-template <> struct PlaneCfg<float, 128> { static constexpr int NT = 512; using FX = Sched<8, 8, 2>; using FY = FX; };
+template <> struct PlaneCfg<float, 128> { static constexpr int NT = 256; using FX = Sched<8, 8, 2>; using FY = FX; };
 template <> struct PlaneCfg<float, 256> {
   static constexpr int NT = 1024; using FX = Sched<8, 8, 4>; using FY = Sched<8, 8, 4>;
 };
