@@ -286,6 +286,15 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_z_c2r_r(const cplx<T>* __re
     }
   }
   __syncthreads();
+  // the input samples of the removed part are fetched before the transform, so their
+  // latency hides behind it
+  const size_t obase = (size_t)b * a.out_field + (size_t)c * a.out_comp + (size_t)y * a.nx + (size_t)xt * a.tx +
+                       2 * line;
+  C pre[E];
+  if (removed && !a.e.on) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) pre[i] = *reinterpret_cast<const C*>(in + obase + (size_t)(p + i * P) * plane);
+  }
   C v[1][E];
   const LdsMap m{1, np, 0};
   F::template run<T, 1, true, false, true>(v, lds, m, line, 0, p, d, tw);
@@ -308,25 +317,13 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_z_c2r_r(const cplx<T>* __re
     }
     return;
   }
-  const size_t obase = (size_t)b * a.out_field + (size_t)c * a.out_comp + (size_t)y * a.nx + (size_t)xt * a.tx +
-                       2 * line;
   if (removed) {
-    constexpr int G2 = E < 8 ? E : 8;      // input samples loaded per group
 #pragma unroll
-    for (int g0 = 0; g0 < E; g0 += G2) {
-      C s[G2];
-#pragma unroll
-      for (int i = 0; i < G2; ++i)
-        if (g0 + i < E) s[i] = *reinterpret_cast<const C*>(in + obase + (size_t)(p + (g0 + i) * P) * plane);
-#pragma unroll
-      for (int i = 0; i < G2; ++i) {
-        if (g0 + i < E) {
-          const C o = mk<T>(v[0][g0 + i].x * scale, v[0][g0 + i].y * scale);
-          const size_t off = obase + (size_t)(p + (g0 + i) * P) * plane;
-          *reinterpret_cast<C*>(removed + off) = mk<T>(s[i].x - o.x, s[i].y - o.y);
-          *reinterpret_cast<C*>(out + off) = o;
-        }
-      }
+    for (int i = 0; i < E; ++i) {
+      const C o = mk<T>(v[0][i].x * scale, v[0][i].y * scale);
+      const size_t off = obase + (size_t)(p + i * P) * plane;
+      *reinterpret_cast<C*>(removed + off) = mk<T>(pre[i].x - o.x, pre[i].y - o.y);
+      *reinterpret_cast<C*>(out + off) = o;
     }
   } else {
 #pragma unroll
