@@ -170,13 +170,16 @@ eq_status eq_plan_reset_stats(eq_plan_t p);
  *            0 = library default (three passes where available and nx <= 128),
  *   tc_zp    (ky, kx) columns per workgroup of the three-pass z projection (must divide ny),
  *   radix4   1: radix-4 stages on x (FP32, nx a power of two in 32 .. 512: the six-component
- *            x kernel then holds 6 x 4 values per lane instead of 6 x 8); ignored elsewhere.
+ *            x kernel then holds 6 x 4 values per lane instead of 6 x 8); ignored elsewhere,
+ *   xsplit   x pass kernel: 2 = six components split over the two halves of a wavefront
+ *            (three rows of E values per lane; needs nx / E to divide 32), 1 = not split,
+ *            0 = library default; reported as 1 or 2.
  * Invalid shapes for this grid return EQ_ERR_ARG (EQ_ERR_SIZE if LDS would exceed the device
  * limit) and leave the plan unchanged.  Every setting computes the same transform; results
  * may differ only by floating-point rounding order when radix16 changes.
  * The EQ_TUNE environment variable ("tx_y=16,tx_z=32,rw_x=4,chunk=32,radix16=2,schedule=5") seeds the
  * tuning at eq_plan.  eq_plan_get_tune reports the settings in effect (defaults resolved). */
-typedef struct { int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4; } eq_tune;
+typedef struct { int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4, xsplit; } eq_tune;
 eq_status eq_plan_tune(eq_plan_t p, const eq_tune* t);
 eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t);
 

@@ -110,7 +110,8 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
             mask |= 2
         if _cost(t16, Z_PASSES) < _cost(t8, Z_PASSES):
             mask |= 4
-    best = {"tx_y": 0, "tx_z": 0, "rw_x": 0, "chunk": 0, "radix16": mask, "schedule": 5, "tc_zp": 0, "radix4": 0}
+    best = {"tx_y": 0, "tx_z": 0, "rw_x": 0, "chunk": 0, "radix16": mask, "schedule": 5, "tc_zp": 0, "radix4": 0,
+            "xsplit": 0}
     base = trial(**best)
     log = {"radix16_all8": t8, "radix16_all16": t16, "default_shapes": base}
 
@@ -128,17 +129,21 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
             if c < best_c:
                 best_v, best_c = v, c
         best[knob] = best_v
-    # radix-4 x stages (fewer registers per lane in the six-component x kernel)
+    # x kernel: six components per lane or split over wavefront halves, radix-8 or
+    # radix-4 stages (fewer registers per lane), rows per workgroup
     best_x = _cost(trial(**best) or {}, X_PASSES) or float("inf")
-    for rw in (0, 1, 2, 4):
-        t = trial(**dict(best, radix4=1, rw_x=rw))
-        if t is None or plan.get_tune()["radix4"] != 1:
-            continue
-        c = _cost(t, X_PASSES)
-        log[f"radix4 rw_x={rw}"] = c
-        if c < best_x:
-            best_x = c
-            best = dict(best, radix4=1, rw_x=rw)
+    for xsplit in (1, 2):
+        for radix4 in (0, 1):
+            for rw in (0, 1, 2, 4, 8):
+                t = trial(**dict(best, xsplit=xsplit, radix4=radix4, rw_x=rw))
+                got = plan.get_tune()
+                if t is None or got["radix4"] != radix4 or got["xsplit"] != xsplit:
+                    continue
+                c = _cost(t, X_PASSES)
+                log[f"xsplit={xsplit} radix4={radix4} rw_x={rw}"] = c
+                if c < best_x:
+                    best_x = c
+                    best = dict(best, xsplit=xsplit, radix4=radix4, rw_x=rw)
     five = trial(**best)
     cost5 = _cost(five, FIVE_PASSES) if five else float("inf")
     # 3. three-pass schedule, where the grid allows it

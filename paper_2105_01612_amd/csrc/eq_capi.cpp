@@ -356,7 +356,7 @@ eq_status check_shapes(const eq_plan_s* p, const Tune& tn) {
   const int ty = pick_tx_y(g, p->ay, eb, tn), tz = pick_tx_z(g, p->az, eb, tn), rw = pick_rw_x(g, p->ax, eb, tn);
   auto round64 = [](int t) { return ((t + 63) / 64) * 64; };
   const int thy = ty * (g.ny / p->ay.E), thz = (tz / 2) * (g.nz / p->az.E);
-  const int thx = (x_threads_per_row(p->ax, eb)) * rw;
+  const int thx = x_threads_per_row(p->ax, eb, tn) * rw;
   if (ty < 1 || g.nx % ty || round64(thy) > max_threads(p->ay)) return fail(EQ_ERR_ARG, "tx_y does not fit this grid");
   if (tz < 2 || (tz & 1) || g.nx % tz || round64(thz) > max_threads(p->az))
     return fail(EQ_ERR_ARG, "tx_z does not fit this grid");
@@ -400,6 +400,7 @@ Tune tune_from_env() {
       else if (key == "chunk") t.chunk = val;
       else if (key == "radix16") t.radix16 = val;
       else if (key == "radix4") t.radix4 = val;
+      else if (key == "xsplit") t.xsplit = val;
       else if (key == "schedule") t.schedule = val;
       else if (key == "tc_zp") t.tc_zp = val;
     }
@@ -810,10 +811,12 @@ eq_status eq_plan_tune(eq_plan_t p, const eq_tune* tv) {
   if (tv->tx_y < 0 || tv->tx_z < 0 || tv->rw_x < 0) return fail(EQ_ERR_ARG, "negative launch shape");
   if (tv->radix16 < -1 || tv->radix16 > 7) return fail(EQ_ERR_ARG, "radix16 must be -1 or a mask of 1|2|4");
   if (tv->radix4 != 0 && tv->radix4 != 1) return fail(EQ_ERR_ARG, "radix4 must be 0 or 1 (x axis)");
+  if (tv->xsplit < 0 || tv->xsplit > 2) return fail(EQ_ERR_ARG, "xsplit must be 0, 1 or 2");
   Tune t;
   t.tx_y = tv->tx_y; t.tx_z = tv->tx_z; t.rw_x = tv->rw_x; t.chunk = tv->chunk;
   t.radix16 = tv->radix16;
   t.radix4 = tv->radix4;
+  t.xsplit = tv->xsplit;
   t.schedule = tv->schedule;
   t.tc_zp = tv->tc_zp;
   DeviceGuard dg(p->device);
@@ -839,6 +842,7 @@ eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t) {
   t->chunk = chunk_planes(p);
   t->radix16 = (p->ax.E == 16 ? 1 : 0) | (p->ay.E == 16 ? 2 : 0) | (p->az.E == 16 ? 4 : 0);
   t->radix4 = p->ax.E == 4 ? 1 : 0;
+  t->xsplit = x_split(p->ax, eb, p->tune) ? 2 : 1;
   const bool plane = use_plane(p, p->tune);
   t->schedule = plane ? 3 : 5;
   t->tc_zp = plane ? pick_tc_zproj(p->g, p->desc.prec == EQ_FP64, p->tune.tc_zp) : 0;

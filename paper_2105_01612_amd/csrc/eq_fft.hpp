@@ -403,6 +403,7 @@ template <int R, int... Rest> struct LcmOf<R, Rest...> {
 // Sched<R...>: compile-time radix schedule (index arithmetic folds, only live stage
 // code is emitted); RtFft<E>: radices read from the FftDesc at run time.
 template <int... Rs> struct Sched {
+  static constexpr bool ct = true;
   static constexpr int N = (Rs * ...);
   static constexpr int nst = sizeof...(Rs);
   static constexpr int E = LcmOf<Rs...>::value;
@@ -415,6 +416,7 @@ template <int... Rs> struct Sched {
 };
 
 template <int E_> struct RtFft {
+  static constexpr bool ct = false;
   static constexpr int E = E_;
   static EQ_HD int len(const FftDesc& d) { return d.n; }
   template <typename T, int NL, bool INV, bool IN_REGS, bool OUT_REGS>

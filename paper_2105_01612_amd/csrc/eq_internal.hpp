@@ -33,6 +33,7 @@ struct Tune {
   int schedule = 0;  // 5 = five passes, 3 = three passes (plane route), 0 = default
   int tc_zp = 0;     // columns per workgroup of the three-pass z projection
   int radix4 = 0;    // 1: radix-4 stages on x (six-component x kernel, FP32 powers of two)
+  int xsplit = 0;    // six-component x kernel split over wavefront halves: 1 = off, 2 = on, 0 = default
 };
 
 // Lateral embedding of a sample in the periodic box (the zero-stress buffer of Sections 3.3
@@ -124,8 +125,9 @@ int pick_tx_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);
 int pick_tx_z(const Geom& g, const AxisFft& az, int elem_bytes, const Tune& tn);
 int pick_rw_x(const Geom& g, const AxisFft& ax, int elem_bytes, const Tune& tn);
 int max_threads(const AxisFft& ax);
-int x_threads_per_row(const AxisFft& ax, int elem_bytes);
-bool x6_radix4_available(int nx, bool fp64);   // radix-4 x schedules exist only for the six-component kernel   // threads of the x pass per (kz, ky) row   // workgroup size limit of the engine that serves this axis
+int x_threads_per_row(const AxisFft& ax, int elem_bytes, const Tune& tn);   // threads of the x pass per (kz, ky) row
+bool x6_radix4_available(int nx, bool fp64);   // radix-4 x schedules exist only for the six-component kernels
+bool x_split(const AxisFft& ax, int elem_bytes, const Tune& tn);   // x pass takes the half-split kernel
 size_t lds_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);
 size_t lds_z(const Geom& g, const AxisFft& az, int elem_bytes, const Tune& tn);
 size_t lds_x(const Geom& g, const AxisFft& ax, int elem_bytes, const Tune& tn);

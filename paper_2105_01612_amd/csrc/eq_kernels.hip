@@ -474,6 +474,27 @@ bool use_x6(const AxisFft& ax) {
   return sizeof(T) == 4;
 }
 bool use_x6_eb(const AxisFft& ax, int eb) { return eb == 8 ? use_x6<float>(ax) : use_x6<double>(ax); }
+// The half-split six-component kernel (three rows per lane): needs an even E, P = nx / E
+// dividing the 32 lanes of a wavefront half, and a compile-time schedule for the axis.
+// Default for E <= 16 (the power-of-two schedules), where halving the registers per lane
+// measured 10-20 % faster; the 3/5-smooth schedules (E = 24, 40) keep their line kernel.
+template <typename T>
+bool x6s_schedule(const AxisFft& ax) {
+  FastArgs<T> f;
+  f.kind = KK_X6S;
+  f.n = ax.d.n;
+  f.E = ax.E;
+  f.d = ax.d;
+  f.dry = true;
+  return ct_launch_pow2<T>(f) || ct_launch_mixed<T>(f);
+}
+bool x_split(const AxisFft& ax, int eb, const Tune& tn) {
+  if (tn.xsplit == 1 || (tn.xsplit == 0 && ax.E > 16)) return false;
+  if (!ax.fast || !ct_enabled() || ax.E % 2 != 0) return false;
+  const int P = ax.d.n / ax.E;
+  if (P < 1 || P > 32 || 32 % P != 0) return false;
+  return eb == 8 ? x6s_schedule<float>(ax) : x6s_schedule<double>(ax);
+}
 bool x6_radix4_available(int nx, bool fp64) {
   AxisFft ax{};
   ax.d.n = nx;
@@ -521,6 +542,11 @@ int pick_tx_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
 int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
   if (tn.rw_x > 0) return tn.rw_x;
   const int P = g.nx / ax.E;
+  if (x_split(ax, eb, tn)) {
+    // two wavefronts per workgroup (measured best), one where LDS would pass 64 KiB
+    const size_t row_lds = (size_t)6 * (g.nx + (g.nx >> kX6Skew) + 1) * eb;
+    return (size_t)(64 / P) * row_lds <= kLdsPreferred ? 64 / P : 32 / P;
+  }
   if (use_x6_eb(ax, eb)) {
     // one thread per (row, p); about 64 threads (one wavefront) per workgroup measured best
     int rw = 64 / P;
@@ -543,7 +569,9 @@ int pick_rw_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
 }
 
 int max_threads(const AxisFft& ax) { return ax.fast ? kMaxFastThreads : kMaxThreads; }
-int x_threads_per_row(const AxisFft& ax, int eb) { return (use_x6_eb(ax, eb) ? 1 : 6) * (ax.d.n / ax.E); }
+int x_threads_per_row(const AxisFft& ax, int eb, const Tune& tn) {
+  return (x_split(ax, eb, tn) ? 2 : use_x6_eb(ax, eb) ? 1 : 6) * (ax.d.n / ax.E);
+}
 
 size_t lds_y(const Geom& g, const AxisFft& ay, int eb, const Tune& tn) {
   return (size_t)pick_tx_y(g, ay, eb, tn) * g.ny * eb;
@@ -552,6 +580,12 @@ size_t lds_z(const Geom& g, const AxisFft& az, int eb, const Tune& tn) {
   return (size_t)(pick_tx_z(g, az, eb, tn) / 2) * g.nz * eb;
 }
 size_t lds_x(const Geom& g, const AxisFft& ax, int eb, const Tune& tn) {
+  if (x_split(ax, eb, tn)) {
+    // six lines per row for every row the (whole-wavefront) workgroup covers
+    const int P = g.nx / ax.E;
+    const int rows = round_threads(2 * P * pick_rw_x(g, ax, eb, tn)) / (2 * P);
+    return (size_t)6 * rows * (g.nx + (g.nx >> kX6Skew) + 1) * eb;
+  }
   const bool six = use_x6_eb(ax, eb);
   const int ls = !ax.fast ? g.nx + 1 : g.nx + (g.nx >> (six ? kX6Skew : kSkew)) + 1;
   const int lines = six ? 3 : 6;     // the six-component kernel transforms three rows at a time
@@ -643,7 +677,13 @@ hipError_t launch_x(cplx<T>* W, const Geom& g, int pl0, int npl, int mode, const
   const size_t lds = lds_x(g, ax, eb, tn);
   const dim3 grid((unsigned)((rows + rw - 1) / rw));
   const int P = g.nx / ax.E;
-  if (ax.fast) {
+  if (ax.fast && x_split(ax, eb, tn)) {
+    FastArgs<T> f = fast_args<T>(KK_X6S, ax, grid, dim3(round_threads(2 * P * rw)), lds, s, tw_x);
+    f.W = W;
+    f.xa = a;
+    f.sym = sym;
+    dispatch_fast<T>(f);
+  } else if (ax.fast) {
     const bool six = use_x6<T>(ax);
     FastArgs<T> f = fast_args<T>(six ? KK_X6 : KK_X, ax, grid, dim3((six ? 1 : 6) * rw * P), lds, s, tw_x);
     f.W = W;

@@ -489,15 +489,107 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x6_r(cplx<T>* __restrict__ 
   }
 }
 
+// Swap between the two halves of a wavefront (v_permlane32_swap exchanges lanes 32..63
+// of its first operand with lanes 0..31 of its second).  Afterwards, in lane l < 32, lo
+// is unchanged and hi holds the lo of lane l + 32; in lane l >= 32, lo holds the hi of
+// lane l - 32 and hi is unchanged.
+__device__ __forceinline__ void half_swap_w(float& lo, float& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+  lo = __uint_as_float(r[0]);
+  hi = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void half_swap_w(double& lo, double& hi) {
+  unsigned long long a = __double_as_longlong(lo), b = __double_as_longlong(hi);
+  const auto r0 = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+  const auto r1 = __builtin_amdgcn_permlane32_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+  lo = __longlong_as_double((long long)(((unsigned long long)r1[0] << 32) | r0[0]));
+  hi = __longlong_as_double((long long)(((unsigned long long)r1[1] << 32) | r0[1]));
+}
+template <typename T>
+__device__ __forceinline__ void half_swap(cplx<T>& lo, cplx<T>& hi) {
+  half_swap_w(lo.x, hi.x);
+  half_swap_w(lo.y, hi.y);
+}
+
+// Six-component x pass split over the halves of a wavefront: lanes 0..31 hold the three
+// normal components (slots 0..2) and lanes 32..63 the three shear components (slots
+// 3..5) of the same rows, E elements p + i*P each, so a lane carries half the registers
+// of k_x6_r and transforms three rows.  For the per-frequency operation the halves
+// divide the frequencies: lanes 0..31 take elements i < E/2, lanes 32..63 elements
+// i >= E/2.  One swap per value brings the six components of a lane's frequency
+// together, a second returns the results to the lanes that own them.  P = nx / E
+// divides 32, so 32 / P rows share a wavefront.
+template <typename T, typename F>
+__global__ __launch_bounds__(kMaxFastThreads) void k_x6s_r(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
+                                                           const cplx<T>* __restrict__ tw,
+                                                           const double* __restrict__ sym) {
+  using C = cplx<T>;
+  constexpr int E = F::E, EH = E / 2;
+  static_assert(E % 2 == 0, "the halves split the elements of a lane in two");
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int nx = F::len(d), P = nx / E;
+  const int lane = threadIdx.x & 63, half = lane >> 5, sub = lane & 31;
+  const int p = sub % P;
+  const int rl = (threadIdx.x >> 6) * (32 / P) + sub / P;   // row of the workgroup
+  const int row = blockIdx.x * a.rw + rl;
+  const bool valid = rl < a.rw && row < a.rows;
+  const size_t cstride = (size_t)a.nzh * a.ny * nx;
+  int kz = 0, ky = 0;
+  const size_t base = valid ? x_row_base(a, row, 0, kz, ky) + (size_t)(3 * half) * cstride + p : 0;
+  C v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[c][i] = valid ? W[base + c * cstride + (size_t)i * P] : mk<T>((T)0, (T)0);
+  const LdsMap m{nx + (nx >> kX6Skew) + 1, 1, kX6Skew};
+  const int line0 = (rl * 2 + half) * 3;
+  if (a.mode & XM_FWD) F::template run<T, 3, false, true, true>(v, lds, m, line0, 1, p, d, tw);
+  if (a.mode & (XM_PROJ | XM_DIV | XM_DISP)) {
+    const double sy = sym[nx + ky], sz = sym[nx + a.ny + kz];
+#pragma unroll
+    for (int j = 0; j < EH; ++j) {
+      C A[6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        A[c] = v[c][j];
+        A[3 + c] = v[c][j + EH];
+        half_swap<T>(A[c], A[3 + c]);        // the six components of element j + half * EH
+      }
+      const double sx = sym[p + (j + half * EH) * P];
+      if (a.mode & XM_PROJ) project_one<T>(A, sx, sy, sz);
+      else vector_op<T>(a.mode, A, sx, sy, sz, a.h);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        half_swap<T>(A[c], A[3 + c]);        // back: component c (lo) or 3 + c (hi) of j and j + EH
+        v[c][j] = A[c];
+        v[c][j + EH] = A[3 + c];
+      }
+    }
+  }
+  if (a.mode & XM_INV) {
+    if (a.mode & XM_FWD) __syncthreads();                  // forward's last stage read LDS
+    F::template run<T, 3, true, true, true>(v, lds, m, line0, 1, p, d, tw);
+  }
+  const bool store = valid && (half == 0 || !(a.mode & (XM_DIV | XM_DISP)));
+  if (store) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < E; ++i) W[base + c * cstride + (size_t)i * P] = v[c][i];
+  }
+}
+
 // ------------------------------------------------------- launch helper -----
 
-enum KernelKind : int { KK_Z_R2C, KK_Z_C2R, KK_Y_FWD, KK_Y_INV, KK_X, KK_X6 };
+enum KernelKind : int { KK_Z_R2C, KK_Z_C2R, KK_Y_FWD, KK_Y_INV, KK_X, KK_X6, KK_X6S };
 
 // Everything one register-engine launch needs; launch_with<T, F> issues it.
 template <typename T>
 struct FastArgs {
   KernelKind kind;
   int n, E;                     // line length and elements per thread of the pass's axis
+  bool dry = false;             // only report whether a compile-time schedule serves the launch
   dim3 grid, block;
   size_t lds;
   hipStream_t s;
@@ -537,6 +629,12 @@ void launch_with(const FastArgs<T>& a) {
       break;
     case KK_X:
       hipLaunchKernelGGL((k_x_r<T, F>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+      break;
+    case KK_X6S:
+      if constexpr (F::ct) {
+        if constexpr (F::E % 2 == 0 && F::N / F::E <= 32)
+          hipLaunchKernelGGL((k_x6s_r<T, F>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+      }
       break;
     default:
       if constexpr (F::E == 8)

@@ -20,7 +20,8 @@ template <typename T, int... Rs>
 bool try_sched(const FastArgs<T>& a) {
   using S = Sched<Rs...>;
   if (a.n != S::N || a.E != S::E || !radices_match<Rs...>(a.d)) return false;
-  launch_with<T, S>(a);
+  if (a.kind == KK_X6S && !(S::N / S::E <= 32)) return false;
+  if (!a.dry) launch_with<T, S>(a);
   return true;
 }
 
@@ -28,9 +29,18 @@ bool try_sched(const FastArgs<T>& a) {
 template <typename T, int... Rs>
 bool try_sched_x6(const FastArgs<T>& a) {
   using S = Sched<Rs...>;
-  if (a.kind != KK_X6 || a.n != S::N || a.E != S::E || !radices_match<Rs...>(a.d)) return false;
-  hipLaunchKernelGGL((k_x6_r<T, S>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
-  return true;
+  if (a.n != S::N || a.E != S::E || !radices_match<Rs...>(a.d)) return false;
+  if (a.kind == KK_X6) {
+    if (!a.dry) hipLaunchKernelGGL((k_x6_r<T, S>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+    return true;
+  }
+  if constexpr (S::N / S::E <= 32) {
+    if (a.kind == KK_X6S) {
+      if (!a.dry) hipLaunchKernelGGL((k_x6s_r<T, S>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+      return true;
+    }
+  }
+  return false;
 }
 
 // powers of two: radix 8 (E = 8) and radix 16 (E = 16)

@@ -224,6 +224,60 @@ def test_radix4_x_parity(op, shape):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("shape,radix,P", [((16, 12, 32), {}, 4), ((20, 6, 64), {}, 8), ((8, 10, 128), {}, 16),
+                                           ((4, 10, 256), {}, 32), ((6, 18, 96), {}, 4), ((6, 10, 160), {}, 4),
+                                           ((4, 6, 192), {}, 8), ((6, 10, 128), {"radix4": 1}, 32),
+                                           ((4, 6, 256), {"radix16": 1}, 16)])
+def test_xsplit_parity(prec, op, shape, radix, P):
+    """The x pass split over wavefront halves (three rows per lane, frequencies divided
+    between the halves): projection, the spectral divergence of the CDO residual and the
+    potential, against the oracle, for ragged row counts and rows per workgroup that do
+    not fill a wavefront.  P = nx / E lanes per row."""
+    eq = eqmod()
+    torch = torch_mod()
+    nz, ny, nx = shape
+    if "radix4" in radix and prec == "fp64":
+        pytest.skip("radix-4 x stages are FP32 only")
+    say("xsplit", prec, op, shape, radix)
+    h = 0.7
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=6, sigma_grain=80.0, sigma_noise=4.0, sigma_grad=1.0,
+                                      seed=nx + ny))
+    Su = upcast(S, prec)
+    ref, ref_rem = O.project(Su, op)
+    ref_pot = O.removed_potential(Su, op, h)
+    ref_norms = O.residual_norms(Su, op, h)
+    plan = eq.plan(nx, ny, nz, op=op, prec=prec, h=h)
+    eb = 8 if prec == "fp32" else 16
+
+    def lds_ok(rw):   # six skewed lines per row of every row the wavefronts cover, within 64 KiB
+        rows = -(-rw * 2 * P // 64) * 64 // (2 * P)
+        return 6 * rows * (nx + nx // 16 + 1) * eb <= 65536
+
+    for rw in [r for r in sorted({0, 1, 3, 32 // P}) if r == 0 or lds_ok(r)]:
+        plan.tune(schedule=5, rw_x=rw, xsplit=2, **radix)
+        assert plan.get_tune()["xsplit"] == 2
+        x = to_dev(S, prec)
+        out = torch.empty_like(x)
+        rem = torch.empty_like(x)
+        plan.project(x, out, rem)
+        assert rel_l2(out.double().cpu().numpy(), ref) <= TOL[prec], rw
+        assert rel_l2(rem.double().cpu().numpy(), ref_rem) <= TOL[prec] * 10, rw
+        Y = plan.potential(x).double().cpu().numpy()
+        assert np.linalg.norm(Y - ref_pot) / np.linalg.norm(ref_pot) <= (1e-11 if prec == "fp64" else 2e-5), rw
+        norms = plan.residual(x)[0]
+        tol = 1e-12 if prec == "fp64" else 2e-5
+        for g, r in zip(norms, ref_norms):
+            assert abs(g - r) <= tol * abs(r), (rw, norms, ref_norms)
+    # the unsplit kernel gives the same projection to rounding
+    plan.tune(schedule=5, xsplit=1, **radix)
+    assert plan.get_tune()["xsplit"] == 1
+    x = to_dev(S, prec)
+    assert rel_l2(plan.project(x).double().cpu().numpy(), ref) <= TOL[prec]
+    plan.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
 @pytest.mark.parametrize("shape", [(4, 6, 1024), (6, 1024, 4), (1024, 4, 6), (4, 6, 960), (1000, 4, 6),
                                    (6, 768, 4)])
 def test_maximum_edges(prec, op, shape):
