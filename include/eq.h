@@ -151,6 +151,12 @@ eq_status eq_plan_set_stream(eq_plan_t p, void* hip_stream);
  * algorithmic bytes (compulsory reads + writes) of one launch.  Graph replay is
  * bypassed while enabled. */
 eq_status eq_plan_set_timing(eq_plan_t p, int enable);
+/* Restrict the instrumentation to the pass named `pass` (a name eq_plan_pass_stats
+ * reports, e.g. "z_c2r"); NULL or "" = every pass.  Each bracketed launch adds two event
+ * records to the stream, so timing one pass keeps the instrumented step close to the
+ * uninstrumented one.  Unknown names return EQ_ERR_ARG.  Timing itself is still switched
+ * by eq_plan_set_timing. */
+eq_status eq_plan_set_timing_pass(eq_plan_t p, const char* pass);
 eq_status eq_plan_pass_stats(eq_plan_t p, int max, int* count, const char** names,
                              long long* launches, double* total_ms, double* bytes_per_launch);
 eq_status eq_plan_reset_stats(eq_plan_t p);

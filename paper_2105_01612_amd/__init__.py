@@ -35,7 +35,7 @@ exported_symbols = (
     "eq_plan", "eq_project", "eq_residual", "eq_plan_destroy", "eq_plan_footprint", "eq_status_str",
     "eq_last_error", "eq_plan_set_stream", "eq_plan_set_timing", "eq_plan_pass_stats",
     "eq_plan_reset_stats", "eq_debug_forward", "eq_debug_project_spectrum", "eq_version", "eq_plan_tune",
-    "eq_plan_get_tune", "eq_potential", "eq_project_embedded",
+    "eq_plan_get_tune", "eq_potential", "eq_project_embedded", "eq_plan_set_timing_pass",
 )
 
 
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
     L.eq_plan_set_stream.argtypes = [vp, vp]
     L.eq_plan_set_timing.argtypes = [vp, ip]
     L.eq_plan_reset_stats.argtypes = [vp]
+    L.eq_plan_set_timing_pass.argtypes = [vp, ctypes.c_char_p]
     L.eq_plan_pass_stats.argtypes = [vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ctypes.c_char_p),
                                      ctypes.POINTER(ctypes.c_longlong), dp, dp]
     L.eq_debug_forward.argtypes = [vp, vp, vp]
@@ -270,7 +271,9 @@ class Plan:
         return {"tx_y": t.tx_y, "tx_z": t.tx_z, "rw_x": t.rw_x, "chunk": t.chunk, "radix16": t.radix16,
                 "schedule": t.schedule, "tc_zp": t.tc_zp, "radix4": t.radix4, "xsplit": t.xsplit}
 
-    def set_timing(self, enable: bool):
+    def set_timing(self, enable: bool, only: str = None):
+        """eq_plan_set_timing; `only` names the one pass to bracket with events (None: all)."""
+        _check(lib().eq_plan_set_timing_pass(self._h, (only or "").encode()), "eq_plan_set_timing_pass")
         _check(lib().eq_plan_set_timing(self._h, 1 if enable else 0), "eq_plan_set_timing")
 
     def reset_stats(self):

@@ -220,6 +220,7 @@ struct eq_plan_s {
   int* flag = nullptr;
   // timing
   bool timing = false;
+  int timing_pass = -1;      // -1: every pass, else the one pass id bracketed by events
   std::vector<TimingRec> pending;
   std::vector<hipEvent_t> event_pool;
   long long launches[P_COUNT] = {};
@@ -285,7 +286,7 @@ hipEvent_t get_event(eq_plan_s* p) {
 // Bracket one launch with events when timing is on.
 template <typename F>
 hipError_t timed(eq_plan_s* p, int pass, F&& launch, double frac = 1.0) {
-  if (!p->timing) return launch();
+  if (!p->timing || (p->timing_pass >= 0 && pass != p->timing_pass)) return launch();
   hipEvent_t a = get_event(p), b = get_event(p);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, p->stream);
@@ -853,6 +854,20 @@ eq_status eq_plan_set_timing(eq_plan_t p, int enable) {
   if (!p) return fail(EQ_ERR_ARG, "null plan");
   p->timing = enable != 0;
   return EQ_OK;
+}
+
+eq_status eq_plan_set_timing_pass(eq_plan_t p, const char* pass) {
+  if (!p) return fail(EQ_ERR_ARG, "null plan");
+  if (!pass || !pass[0]) {
+    p->timing_pass = -1;
+    return EQ_OK;
+  }
+  for (int i = 0; i < P_COUNT; ++i)
+    if (std::strcmp(kPassNames[i], pass) == 0) {
+      p->timing_pass = i;
+      return EQ_OK;
+    }
+  return fail(EQ_ERR_ARG, std::string("unknown pass ") + pass);
 }
 
 eq_status eq_plan_reset_stats(eq_plan_t p) {

@@ -565,6 +565,16 @@ def test_timing_stats():
         assert st[name]["launches"] == 3 and st[name]["total_ms"] > 0 and st[name]["bytes_per_launch"] > 0
     plan.reset_stats()
     assert plan.pass_stats()["x_proj"]["launches"] == 0
+    # one pass bracketed: only its launches are counted
+    plan.set_timing(True, only="z_c2r")
+    out = plan.project(x)
+    plan.residual(out)
+    st = plan.pass_stats()
+    assert st["z_c2r"]["launches"] == 1 and st["z_c2r"]["total_ms"] > 0
+    assert all(v["launches"] == 0 for k, v in st.items() if k != "z_c2r")
+    with pytest.raises(eq.EqError):
+        plan.set_timing(True, only="no_such_pass")
+    plan.set_timing(False)
     plan.destroy()
     plan = eq.plan(64, op="ddo", prec="fp32")
     x = to_dev(wl.voronoi_field(wl.FieldSpec((64, 64, 64), grains=20, sigma_grain=100.0, sigma_noise=5.0, seed=4)), "fp32")
