@@ -585,7 +585,7 @@ eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out
            }),
            "div_stats launch");
   }
-  const int nred = p->desc.op == EQ_OP_DDO ? div_ddo_blocks(g, kRedBlocks) : kRedBlocks;
+  const int nred = p->desc.op == EQ_OP_DDO ? div_ddo_blocks(g, kRedBlocks, p->desc.prec == EQ_FP64) : kRedBlocks;
   EQ_HIP(timed(p, P_REDUCE, [&] { return launch_reduce_final(p->partials, nred, g.batch, p->red_dev, st); }),
          "reduce launch");
   EQ_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");

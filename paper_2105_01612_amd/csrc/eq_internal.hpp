@@ -90,7 +90,7 @@ constexpr int kRedWidth = 14;
 template <typename T>
 hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk_max, const Geom& g, double h,
                           hipStream_t s);
-int div_ddo_blocks(const Geom& g, int nblk_max);
+int div_ddo_blocks(const Geom& g, int nblk_max, bool fp64);
 
 template <typename T>
 hipError_t launch_div_stats(const T* div, size_t div_field, size_t div_comp, const T* S, double* partials,

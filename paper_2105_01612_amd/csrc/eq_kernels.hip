@@ -282,10 +282,9 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
   const int lx = threadIdx.x % a.tx, ly = threadIdx.x / a.tx;
   const int items = a.tiles * a.zc;
-  // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous run of
-  // work items, so the y-halo rows of neighbouring tiles are read from its own L2
-  int lb = blockIdx.x;
-  if ((gridDim.x & 7) == 0) lb = (lb & 7) * (gridDim.x >> 3) + (lb >> 3);
+  // each XCD takes a contiguous run of work items, so the y-halo rows of neighbouring
+  // tiles are read from its own L2
+  const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
   const T* F0 = F;
   const T* F1 = F + M;
   const T* F2 = F + 2 * M;
@@ -725,7 +724,28 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
   return hipGetLastError();
 }
 
-static DArgs div_ddo_shape(const Geom& g, int nblk_max, double h) {
+// Workgroups of k_div_ddo<T> the device holds at once (CUs x resident workgroups per CU).
+template <typename T>
+int div_ddo_capacity() {
+  static const int cap = [] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_div_ddo<T>), kRedThreads,
+                                                     0) != hipSuccess)
+      return 0;
+    return cus * per;
+  }();
+  return cap;
+}
+
+// Tiles of tx x (2 ty) columns, z chunks per column; a work item is (tile, z chunk), and the
+// grid of a field (at most the device's resident capacity, at most nblk_max) loops over the
+// items.  The kernel lasts (rounds) x (planes per item), so the chunk count is the one that
+// wastes least of the resident capacity for one field (the fewest items on ties).  The
+// shape depends on the field, not on the batch, so a field's partial sums, and so its
+// norms, come out the same alone or in a batch.
+static DArgs div_ddo_shape(const Geom& g, int nblk_max, double h, int cap) {
   DArgs a{};
   a.nx = g.nx; a.ny = g.ny; a.nz = g.nz;
   // widest x tile that divides nx (full rows at 256): long row segments, x halo in-tile
@@ -735,26 +755,34 @@ static DArgs div_ddo_shape(const Geom& g, int nblk_max, double h) {
   a.ty = kRedThreads / a.tx;                 // thread rows; each thread takes two grid rows
   a.tiles_x = (g.nx + a.tx - 1) / a.tx;
   a.tiles = a.tiles_x * ((g.ny + 2 * a.ty - 1) / (2 * a.ty));
-  // z chunks: as many as fit the partial records, at least 8 planes per march where possible
-  int zc = nblk_max / a.tiles;
-  zc = zc < 1 ? 1 : zc;
-  const int zmax = g.nz >= 16 ? g.nz / 8 : 1;
-  a.zc = zc < zmax ? zc : zmax;
+  const int G = cap > 0 && cap < nblk_max ? cap : nblk_max;
+  const int zmax = g.nz >= 16 ? g.nz / 8 : 1;   // at least 8 planes per march where possible
+  double best = -1.0;
+  a.zc = 1;
+  for (int zc = 1; zc <= zmax; ++zc) {
+    const long items = (long)a.tiles * zc;
+    const long grid = items < G ? items : G;
+    const long rounds = (items + grid - 1) / grid;
+    const double eff = ((double)a.tiles * g.nz / G) / ((double)rounds * ((g.nz + zc - 1) / zc));
+    if (eff > best + 1e-9) { best = eff; a.zc = zc; }
+  }
   a.inv2h = 0.5 / h;
   return a;
 }
 
-int div_ddo_blocks(const Geom& g, int nblk_max) {
-  const DArgs a = div_ddo_shape(g, nblk_max, 1.0);
-  const int items = a.tiles * a.zc;
-  return items < nblk_max ? items : nblk_max;
+int div_ddo_blocks(const Geom& g, int nblk_max, bool fp64) {
+  const int cap = fp64 ? div_ddo_capacity<double>() : div_ddo_capacity<float>();
+  const DArgs a = div_ddo_shape(g, nblk_max, 1.0, cap);
+  const int G = cap > 0 && cap < nblk_max ? cap : nblk_max;
+  const long items = (long)a.tiles * a.zc;
+  return (int)(items < G ? items : G);
 }
 
 template <typename T>
 hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk_max, const Geom& g, double h, hipStream_t s) {
-  const DArgs a = div_ddo_shape(g, nblk_max, h);
-  hipLaunchKernelGGL((k_div_ddo<T>), dim3(div_ddo_blocks(g, nblk_max), g.batch), dim3(kRedThreads), 0, s, S, div_out,
-                     partials, a);
+  const DArgs a = div_ddo_shape(g, nblk_max, h, div_ddo_capacity<T>());
+  hipLaunchKernelGGL((k_div_ddo<T>), dim3(div_ddo_blocks(g, nblk_max, sizeof(T) == 8), g.batch), dim3(kRedThreads), 0,
+                     s, S, div_out, partials, a);
   return hipGetLastError();
 }
 

@@ -122,6 +122,15 @@ __device__ __forceinline__ void vector_op(int mode, cplx<T>* A, double sx, doubl
   else divergence_one<T>(A, sx, sy, sz);
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (workgroup b to XCD b mod 8).  This
+// bijection of [0, n) gives each XCD a contiguous run of work indices, so neighbouring
+// work items share the lines of their XCD's L2: XCD x takes n/8 indices, one more when
+// x < n mod 8, starting after those of the XCDs before it.
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // ------------------------------------------------------------ arguments ----
 
 struct ZArgs {
