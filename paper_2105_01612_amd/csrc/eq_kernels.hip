@@ -264,19 +264,50 @@ struct DArgs {
   double inv2h;
 };
 
+// Element e of component c of one field: a raw buffer load when every component's byte
+// range fits the 32-bit offset (the six resources sit in SGPRs and one 32-bit offset per
+// neighbour serves all six components), else a plain load.
+template <typename T, bool BUF>
+struct FieldReader {
+  const T* f[6];
+  __amdgpu_buffer_rsrc_t r[6];
+  __device__ FieldReader(const T* F, size_t M) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      f[c] = F + c * M;
+      if constexpr (BUF) r[c] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f[c]), 0, (int)(M * sizeof(T)), kBufWord3);
+    }
+  }
+  __device__ __forceinline__ double operator()(int c, size_t e) const {
+    if constexpr (BUF) {
+      const unsigned off = (unsigned)e * (unsigned)sizeof(T);
+      if constexpr (sizeof(T) == 4) {
+        return (double)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r[c], off, 0, 0));
+      } else {
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b64(r[c], off, 0, 0);
+        double v;
+        __builtin_memcpy(&v, &raw, sizeof(v));
+        return v;
+      }
+    } else {
+      return (double)f[c][e];
+    }
+  }
+};
+
 // DDO divergence in real space: periodic central differences, exactly the DDO symbol.
 // A thread owns rows y and y + 1 of one x column of a z chunk and marches along z: the
 // three components differentiated along z (S33, S23, S13) roll through registers, each
 // row is the other's y neighbour for S12, S22 and S23, and only rows y - 1 and y + 2
 // come from neighbouring tiles (15 loads per voxel instead of 18).
-template <typename T>
+template <typename T, bool BUF>
 __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S, T* __restrict__ div,
                                                          double* __restrict__ partials, DArgs a) {
   __shared__ double sh[kRedWidth * kRedThreads];
   const int b = blockIdx.y;
   const size_t M = (size_t)a.nx * a.ny * a.nz;
   const size_t sz = (size_t)a.nx * a.ny;
-  const T* F = S + (size_t)b * 6 * M;
+  const FieldReader<T, BUF> F(S + (size_t)b * 6 * M, M);
   double acc[kRedWidth];
 #pragma unroll
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
@@ -285,12 +316,6 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
   // each XCD takes a contiguous run of work items, so the y-halo rows of neighbouring
   // tiles are read from its own L2
   const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
-  const T* F0 = F;
-  const T* F1 = F + M;
-  const T* F2 = F + 2 * M;
-  const T* F3 = F + 3 * M;
-  const T* F4 = F + 4 * M;
-  const T* F5 = F + 5 * M;
   for (int it = lb; it < items; it += gridDim.x) {
     const int tile = it % a.tiles, zi = it / a.tiles;
     const int x = (tile % a.tiles_x) * a.tx + lx;
@@ -305,31 +330,25 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
     const long dxm = (x == 0) ? (long)a.nx - 1 : -1;
     const size_t pm = (size_t)(z0 == 0 ? a.nz - 1 : z0 - 1) * sz;
     const size_t p0 = (size_t)z0 * sz;
-    double a2m = F2[pm + ca], a3m = F3[pm + ca], a4m = F4[pm + ca];
-    double a2c = F2[p0 + ca], a3c = F3[p0 + ca], a4c = F4[p0 + ca];
-    double b2m = F2[pm + cb], b3m = F3[pm + cb], b4m = F4[pm + cb];
-    double b2c = F2[p0 + cb], b3c = F3[p0 + cb], b4c = F4[p0 + cb];
+    double a2m = F(2, pm + ca), a3m = F(3, pm + ca), a4m = F(4, pm + ca);
+    double a2c = F(2, p0 + ca), a3c = F(3, p0 + ca), a4c = F(4, p0 + ca);
+    double b2m = F(2, pm + cb), b3m = F(3, pm + cb), b4m = F(4, pm + cb);
+    double b2c = F(2, p0 + cb), b3c = F(3, p0 + cb), b4c = F(4, p0 + cb);
     for (int z = z0; z < z1; ++z) {
       const size_t p = (size_t)z * sz;
       const size_t pn = (size_t)(z + 1 == a.nz ? 0 : z + 1) * sz;
-      const double a2p = F2[pn + ca], a3p = F3[pn + ca], a4p = F4[pn + ca];
-      const double b2p = F2[pn + cb], b3p = F3[pn + cb], b4p = F4[pn + cb];
-      const double a0 = F0[p + ca], a1 = F1[p + ca], a5 = F5[p + ca];
-      const double b0 = F0[p + cb], b1 = F1[p + cb], b5 = F5[p + cb];
+      const double a2p = F(2, pn + ca), a3p = F(3, pn + ca), a4p = F(4, pn + ca);
+      const double b2p = F(2, pn + cb), b3p = F(3, pn + cb), b4p = F(4, pn + cb);
+      const double a0 = F(0, p + ca), a1 = F(1, p + ca), a5 = F(5, p + ca);
+      const double b0 = F(0, p + cb), b1 = F(1, p + cb), b5 = F(5, p + cb);
       const size_t qa = p + ca, qb = p + cb;
       // r_x = d_x S11 + d_y S12 + d_z S13, etc. (slots 0=11 1=22 2=33 3=23 4=13 5=12)
-      const double ra0 = (((double)F0[qa + dxp] - (double)F0[qa + dxm]) + (b5 - (double)F5[p + ym]) + (a4p - a4m)) *
-                         a.inv2h;
-      const double ra1 = (((double)F5[qa + dxp] - (double)F5[qa + dxm]) + (b1 - (double)F1[p + ym]) + (a3p - a3m)) *
-                         a.inv2h;
-      const double ra2 = (((double)F4[qa + dxp] - (double)F4[qa + dxm]) + (b3c - (double)F3[p + ym]) + (a2p - a2m)) *
-                         a.inv2h;
-      const double rb0 = (((double)F0[qb + dxp] - (double)F0[qb + dxm]) + ((double)F5[p + yq] - a5) + (b4p - b4m)) *
-                         a.inv2h;
-      const double rb1 = (((double)F5[qb + dxp] - (double)F5[qb + dxm]) + ((double)F1[p + yq] - a1) + (b3p - b3m)) *
-                         a.inv2h;
-      const double rb2 = (((double)F4[qb + dxp] - (double)F4[qb + dxm]) + ((double)F3[p + yq] - a3c) + (b2p - b2m)) *
-                         a.inv2h;
+      const double ra0 = ((F(0, qa + dxp) - F(0, qa + dxm)) + (b5 - F(5, p + ym)) + (a4p - a4m)) * a.inv2h;
+      const double ra1 = ((F(5, qa + dxp) - F(5, qa + dxm)) + (b1 - F(1, p + ym)) + (a3p - a3m)) * a.inv2h;
+      const double ra2 = ((F(4, qa + dxp) - F(4, qa + dxm)) + (b3c - F(3, p + ym)) + (a2p - a2m)) * a.inv2h;
+      const double rb0 = ((F(0, qb + dxp) - F(0, qb + dxm)) + (F(5, p + yq) - a5) + (b4p - b4m)) * a.inv2h;
+      const double rb1 = ((F(5, qb + dxp) - F(5, qb + dxm)) + (F(1, p + yq) - a1) + (b3p - b3m)) * a.inv2h;
+      const double rb2 = ((F(4, qb + dxp) - F(4, qb + dxm)) + (F(3, p + yq) - a3c) + (b2p - b2m)) * a.inv2h;
       const double ma = ra0 * ra0 + ra1 * ra1 + ra2 * ra2;
       const double mb = rb0 * rb0 + rb1 * rb1 + rb2 * rb2;
       acc[0] += ma + mb;
@@ -724,19 +743,29 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
   return hipGetLastError();
 }
 
-// Workgroups of k_div_ddo<T> the device holds at once (CUs x resident workgroups per CU).
+// Buffer loads need each component's byte range below 2^31.
 template <typename T>
+bool div_ddo_buf(const Geom& g) {
+  return (double)g.nx * g.ny * g.nz * sizeof(T) < 2147483648.0;
+}
+
+// Workgroups of k_div_ddo<T, BUF> the device holds at once (CUs x resident workgroups per CU).
+template <typename T, bool BUF>
 int div_ddo_capacity() {
   static const int cap = [] {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_div_ddo<T>), kRedThreads,
-                                                     0) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_div_ddo<T, BUF>),
+                                                     kRedThreads, 0) != hipSuccess)
       return 0;
     return cus * per;
   }();
   return cap;
+}
+template <typename T>
+int div_ddo_cap(const Geom& g) {
+  return div_ddo_buf<T>(g) ? div_ddo_capacity<T, true>() : div_ddo_capacity<T, false>();
 }
 
 // Tiles of tx x (2 ty) columns, z chunks per column; a work item is (tile, z chunk), and the
@@ -771,7 +800,7 @@ static DArgs div_ddo_shape(const Geom& g, int nblk_max, double h, int cap) {
 }
 
 int div_ddo_blocks(const Geom& g, int nblk_max, bool fp64) {
-  const int cap = fp64 ? div_ddo_capacity<double>() : div_ddo_capacity<float>();
+  const int cap = fp64 ? div_ddo_cap<double>(g) : div_ddo_cap<float>(g);
   const DArgs a = div_ddo_shape(g, nblk_max, 1.0, cap);
   const int G = cap > 0 && cap < nblk_max ? cap : nblk_max;
   const long items = (long)a.tiles * a.zc;
@@ -780,9 +809,12 @@ int div_ddo_blocks(const Geom& g, int nblk_max, bool fp64) {
 
 template <typename T>
 hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk_max, const Geom& g, double h, hipStream_t s) {
-  const DArgs a = div_ddo_shape(g, nblk_max, h, div_ddo_capacity<T>());
-  hipLaunchKernelGGL((k_div_ddo<T>), dim3(div_ddo_blocks(g, nblk_max, sizeof(T) == 8), g.batch), dim3(kRedThreads), 0,
-                     s, S, div_out, partials, a);
+  const DArgs a = div_ddo_shape(g, nblk_max, h, div_ddo_cap<T>(g));
+  const dim3 grid(div_ddo_blocks(g, nblk_max, sizeof(T) == 8), g.batch);
+  if (div_ddo_buf<T>(g))
+    hipLaunchKernelGGL((k_div_ddo<T, true>), grid, dim3(kRedThreads), 0, s, S, div_out, partials, a);
+  else
+    hipLaunchKernelGGL((k_div_ddo<T, false>), grid, dim3(kRedThreads), 0, s, S, div_out, partials, a);
   return hipGetLastError();
 }
 

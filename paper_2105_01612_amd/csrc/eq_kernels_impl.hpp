@@ -122,6 +122,12 @@ __device__ __forceinline__ void vector_op(int mode, cplx<T>* A, double sx, doubl
   else divergence_one<T>(A, sx, sy, sz);
 }
 
+// Word 3 of a raw buffer resource on gfx9: 32-bit data format, no swizzle.  A buffer load
+// takes a 32-bit byte offset (VGPR) plus a workgroup-uniform one (SGPR) against a base
+// held in SGPRs, so per-lane addresses cost one register instead of two; reads outside
+// the resource's range return 0.
+constexpr int kBufWord3 = 0x00020000;
+
 // Workgroups are dealt round-robin to the 8 XCDs (workgroup b to XCD b mod 8).  This
 // bijection of [0, n) gives each XCD a contiguous run of work indices, so neighbouring
 // work items share the lines of their XCD's L2: XCD x takes n/8 indices, one more when

@@ -247,10 +247,8 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2
 
 // ------------------------------------------------------------ z pass -------
 
-// Raw buffer access (gfx9 resource word 3: 32-bit data format, no swizzle); the range
-// in the resource is the field's byte size.
-constexpr int kBufWord3 = 0x00020000;
-
+// Raw buffer access (resource word 3 in eq_kernels_impl.hpp); the range in the resource
+// is the field's byte size.
 template <typename T>
 __device__ __forceinline__ cplx<T> buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   cplx<T> v;
