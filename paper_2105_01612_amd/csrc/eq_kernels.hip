@@ -743,9 +743,12 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
   return hipGetLastError();
 }
 
-// Buffer loads need each component's byte range below 2^31.
+// Buffer loads need each component's byte range below 2^31 (EQ_DDO_BUF=0 forces plain
+// loads, so that both paths can be compared on small grids).
 template <typename T>
 bool div_ddo_buf(const Geom& g) {
+  const char* e = std::getenv("EQ_DDO_BUF");
+  if (e && e[0] == '0') return false;
   return (double)g.nx * g.ny * g.nz * sizeof(T) < 2147483648.0;
 }
 

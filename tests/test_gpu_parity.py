@@ -475,6 +475,27 @@ def test_residual_parity(op, prec, shape):
     plan.destroy()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_residual_plain_load_path(prec, monkeypatch):
+    """The DDO stencil's plain-load path (taken when a component array passes 2 GB)
+    against the oracle, forced on a small grid."""
+    eq = eqmod()
+    shape = (40, 32, 96)
+    nz, ny, nx = shape
+    h = 0.8
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=10, sigma_grain=50.0, sigma_noise=3.0, seed=5))
+    Su = upcast(S, prec)
+    ref = O.residual_norms(Su, "ddo", h)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for flag in ("0", "1"):
+        monkeypatch.setenv("EQ_DDO_BUF", flag)
+        plan = eq.plan(nx, ny, nz, op="ddo", prec=prec, h=h)
+        norms = plan.residual(to_dev(S, prec))[0]
+        for g, r in zip(norms, ref):
+            assert abs(g - r) <= tol * abs(r), (flag, norms, ref)
+        plan.destroy()
+
+
 def test_residual_of_projection_is_roundoff():
     eq = eqmod()
     n = 64
