@@ -408,10 +408,17 @@ def main():
         "roofline": roof,
         "passes": per_pass,
         "hbm_frac_144B_schedule_min": (vox / r32["elapsed_s"] * args.steps) * 144 / (HBM_PEAK_GBS * 1e9),
+        # read S, write S_eq only: what a fully fused path would still move
+        "hbm_frac_compulsory_48B": (vox / r32["elapsed_s"] * args.steps) * 48 / (HBM_PEAK_GBS * 1e9),
         "residual_of_output": r32["norms"][0] if r32["norms"] else None,
         "tune": r32["tune"],
         "paper_context": PAPER_CONTEXT,
     }
+    if r32["all_stats"]:
+        # algorithmic bytes of every launch of one step, and the rate the whole step sustains
+        step_bytes = sum(st["bytes_per_launch"] * st["launches"] for st in r32["all_stats"].values()) / args.steps
+        line["step_bytes_per_voxel"] = round(step_bytes / vox, 2)
+        line["hbm_frac_step_bytes"] = step_bytes / (ms32 * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     if not args.no_compare and args.workload != "batched":
         S64 = S32.astype(np.float64)
