@@ -1,0 +1,72 @@
+"""Host logic of bench.py (no GPU): the slowest-kernel choice, the roofline arithmetic,
+the counter-record lookup keyed by the kernel-source digest, and the one-GPU guard."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def stats(**avg_ms):
+    """pass_stats-shaped records: 10 launches, 1 GB per launch, the given average time."""
+    return {k: {"launches": 10, "total_ms": 10 * v, "bytes_per_launch": 1e9} for k, v in avg_ms.items()}
+
+
+def test_slowest_pass_ignores_non_projection_kernels():
+    st = stats(z_r2c=0.15, x_proj=0.18, z_c2r=0.32, div_ddo=0.11, reduce_final=5.0)
+    assert bench.slowest_pass(st) == "z_c2r"
+    st["z_c2r"]["launches"] = 0
+    assert bench.slowest_pass(st) == "x_proj"
+    assert bench.slowest_pass({}) is None
+
+
+def test_roofline_arithmetic():
+    timed = stats(z_c2r=0.25)                       # only the slowest kernel bracketed
+    table = stats(z_r2c=0.125, z_c2r=0.25)          # every kernel, earlier steps
+    roof, per_pass = bench.roofline(timed, table, "no_such_workload")
+    assert roof["kernel"] == "z_c2r" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
+    assert roof["achieved"] == pytest.approx(4000.0)          # 1 GB in 0.25 ms
+    assert roof["peak"] == bench.HBM_PEAK_GBS
+    assert roof["frac"] == pytest.approx(0.5)
+    assert roof["traffic"] is None                             # no counter record for this workload
+    assert set(per_pass) == {"z_r2c", "z_c2r"}
+    assert per_pass["z_r2c"]["GB_s"] == pytest.approx(8000.0)
+
+
+def test_traffic_record_requires_current_sources(tmp_path, monkeypatch):
+    rec = {"z_c2r@w": {"traffic_bytes": 123.0, "source_digest": "a" * 16},
+           "x_proj@w": {"traffic_bytes": 456.0, "source_digest": "b" * 16}}
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "a" * 16)
+    assert bench.load_traffic("z_c2r", "w") == 123.0
+    assert bench.load_traffic("x_proj", "w") is None          # counted on other kernel sources
+    assert bench.load_traffic("z_r2c", "w") is None           # never profiled
+
+
+def test_kernel_source_digest_tracks_the_sources():
+    d = bench.kernel_source_digest()
+    assert len(d) == 16 and int(d, 16) >= 0
+    assert bench.kernel_source_digest() == d
+
+
+def test_committed_traffic_records_name_their_summaries():
+    data = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    assert data
+    for key, rec in data.items():
+        assert os.path.exists(os.path.join(ROOT, rec["summary"])), key
+        assert rec["traffic_bytes"] > 0 and len(rec["source_digest"]) == 16, key
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
