@@ -185,6 +185,16 @@ def frob_err(got, ref):
     return math.sqrt(float(np.sum(w * d * d)) / float(np.sum(w * ref * ref))), float(np.abs(d).max())
 
 
+def roundoff_amplification(S, S_eq):
+    """||S - c0|| / ||S_eq - c0|| (Frobenius, off-diagonals twice; c0 = the per-component
+    mean): the factor by which the input's round-off grows relative to the output."""
+    w = np.array([1, 1, 1, 2, 2, 2], dtype=np.float64).reshape(6, 1, 1, 1)
+    c0 = S.mean(axis=(1, 2, 3), keepdims=True)
+    num = float(np.sum(w * (S - c0) ** 2))
+    den = float(np.sum(w * (S_eq - c0) ** 2))
+    return math.sqrt(num / den) if den > 0 else None
+
+
 def cpu_baseline(S_field64, op):
     """The FP64 oracle on the host, on one whole field (the bounded sample)."""
     import oracle
@@ -438,7 +448,8 @@ def main():
             e32 = frob_err(r32["out"].numpy()[:1], ref[None])
             e64 = frob_err(r64["out"].numpy()[:1], ref[None])
             line["error_vs_oracle"] = {"fp32": {"rel_l2": e32[0], "max_abs_mpa": e32[1], "tol": 1e-5},
-                                       "fp64": {"rel_l2": e64[0], "max_abs_mpa": e64[1], "tol": 1e-12}}
+                                       "fp64": {"rel_l2": e64[0], "max_abs_mpa": e64[1], "tol": 1e-12},
+                                       "roundoff_amplification": roundoff_amplification(S64[0], ref)}
             log(f"[bench] oracle {cb['sample']}; fp32 rel-L2 {e32[0]:.2e}, fp64 rel-L2 {e64[0]:.2e}")
     print(json.dumps(line), flush=True)
 

@@ -65,6 +65,17 @@ def test_committed_traffic_records_name_their_summaries():
         assert rec["traffic_bytes"] > 0 and len(rec["source_digest"]) == 16, key
 
 
+def test_roundoff_amplification():
+    import numpy as np
+
+    rng = np.random.default_rng(1)
+    S = rng.standard_normal((6, 4, 4, 4)) + 3.0
+    assert bench.roundoff_amplification(S, S) == pytest.approx(1.0)
+    c0 = S.mean(axis=(1, 2, 3), keepdims=True)
+    assert bench.roundoff_amplification(S, c0 + 0.5 * (S - c0)) == pytest.approx(2.0)
+    assert bench.roundoff_amplification(S, np.broadcast_to(c0, S.shape)) is None
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
