@@ -415,6 +415,8 @@ def main():
                    "grid": [nx, ny, nz], "batch": B, "op": args.op, "prec": "fp32"},
         "p50_ms": statistics.median(r32["lat_ms"]),
         "p99_ms": float(np.percentile(r32["lat_ms"], 99)),
+        "p10_ms": float(np.percentile(r32["lat_ms"], 10)),
+        "p90_ms": float(np.percentile(r32["lat_ms"], 90)),
         "roofline": roof,
         "passes": per_pass,
         "hbm_frac_144B_schedule_min": (vox / r32["elapsed_s"] * args.steps) * 144 / (HBM_PEAK_GBS * 1e9),
