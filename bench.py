@@ -355,8 +355,8 @@ def main():
         os.environ["EQ_AUTOTUNE_CACHE"] = os.path.abspath(args.tune_cache)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs every field on a single MI355X "
-              "(multi-GPU sharding is a design note, not built). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: every field runs on a single MI355X "
+              "(sharding across GPUs is described, not implemented). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
