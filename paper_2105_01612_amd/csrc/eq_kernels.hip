@@ -493,7 +493,8 @@ bool use_x6(const AxisFft& ax) {
 }
 bool use_x6_eb(const AxisFft& ax, int eb) { return eb == 8 ? use_x6<float>(ax) : use_x6<double>(ax); }
 // The half-split six-component kernel (three rows per lane): needs an even E, P = nx / E
-// dividing the 32 lanes of a wavefront half, and a compile-time schedule for the axis.
+// dividing the 32 lanes of a wavefront half (k_x6s_r) or P = 64, one wavefront per
+// component triple (k_x6w_r), and a compile-time schedule for the axis.
 // Default for E <= 16 (the power-of-two schedules), where halving the registers per lane
 // measured 10-20 % faster; the 3/5-smooth schedules (E = 24, 40) keep their line kernel.
 template <typename T>
@@ -510,7 +511,7 @@ bool x_split(const AxisFft& ax, int eb, const Tune& tn) {
   if (tn.xsplit == 1 || (tn.xsplit == 0 && ax.E > 16)) return false;
   if (!ax.fast || !ct_enabled() || ax.E % 2 != 0) return false;
   const int P = ax.d.n / ax.E;
-  if (P < 1 || P > 32 || 32 % P != 0) return false;
+  if (P < 1 || (P > 32 && P != 64) || (P <= 32 && 32 % P != 0)) return false;
   return eb == 8 ? x6s_schedule<float>(ax) : x6s_schedule<double>(ax);
 }
 bool x6_radix4_available(int nx, bool fp64) {

@@ -595,6 +595,102 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_x6s_r(cplx<T>* __restrict__
   }
 }
 
+// Select between two complex values by value (a conditional on array elements would
+// select their addresses and keep the arrays out of registers).
+template <typename T>
+__device__ __forceinline__ cplx<T> csel(bool s, cplx<T> a, cplx<T> b) {
+  return mk<T>(s ? a.x : b.x, s ? a.y : b.y);
+}
+
+// The same split for lines of 64 threads (P = nx / E = 64, e.g. 512 = 64 x 8): the three
+// normal components of a row sit in one wavefront and the three shear components in the
+// next, so the per-frequency exchange goes through LDS instead of a lane swap.  Wavefront
+// h of row r takes frequencies i in [h E/2, (h + 1) E/2): it writes its components of the
+// other half to LDS, reads the other wavefront's components of its own half, evaluates
+// the operation, keeps its own components and writes the other wavefront's back.  The
+// exchange reuses the row's six FFT lines (3 * E * 64 values fit in them).
+template <typename T, typename F>
+__global__ __launch_bounds__(kMaxFastThreads) void k_x6w_r(cplx<T>* __restrict__ W, XArgs a, FftDesc d,
+                                                           const cplx<T>* __restrict__ tw,
+                                                           const double* __restrict__ sym) {
+  using C = cplx<T>;
+  constexpr int E = F::E, EH = E / 2, P = 64;
+  static_assert(E % 2 == 0 && F::N / F::E == 64, "one wavefront per component triple of a line");
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int nx = F::len(d);
+  const int p = threadIdx.x & 63, w = threadIdx.x >> 6, h = w & 1, rl = w >> 1;
+  const int row = blockIdx.x * a.rw + rl;
+  const bool valid = rl < a.rw && row < a.rows;
+  const size_t cstride = (size_t)a.nzh * a.ny * nx;
+  int kz = 0, ky = 0;
+  const size_t base = valid ? x_row_base(a, row, 0, kz, ky) + (size_t)(3 * h) * cstride + p : 0;
+  C v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[c][i] = valid ? W[base + c * cstride + (size_t)i * P] : mk<T>((T)0, (T)0);
+  const LdsMap m{nx + (nx >> kX6Skew) + 1, 1, kX6Skew};
+  const int line0 = (rl * 2 + h) * 3;
+  if (a.mode & XM_FWD) F::template run<T, 3, false, true, true>(v, lds, m, line0, 1, p, d, tw);
+  if (a.mode & (XM_PROJ | XM_DIV | XM_DISP)) {
+    // per row: X_h, then Y_h, each 3 * EH * 64 values, in the row's own six lines
+    C* rowl = lds + (size_t)rl * 6 * m.ls;
+    C* X = rowl;
+    C* Y = rowl + 2 * 3 * EH * P;
+    auto at = [&](int hh, int c, int j) { return (hh * 3 * EH + c * EH + j) * P + p; };
+    __syncthreads();                                        // the forward's last stage read LDS
+    // (register indices stay compile-time: the wavefront's half picks values by select)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < EH; ++j) X[at(h, c, j)] = csel<T>(h, v[c][j], v[c][j + EH]);
+    __syncthreads();
+    const double sy = sym[nx + ky], sz = sym[nx + a.ny + kz];
+#pragma unroll
+    for (int j = 0; j < EH; ++j) {
+      C A[6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const C other = X[at(1 - h, c, j)];
+        const C own = csel<T>(h, v[c][j + EH], v[c][j]);
+        A[c] = csel<T>(h, other, own);
+        A[3 + c] = csel<T>(h, own, other);
+      }
+      const double sx = sym[p + (j + h * EH) * P];
+      if (a.mode & XM_PROJ) project_one<T>(A, sx, sy, sz);
+      else vector_op<T>(a.mode, A, sx, sy, sz, a.h);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v[c][j + EH] = csel<T>(h, A[3 + c], v[c][j + EH]);
+        v[c][j] = csel<T>(h, v[c][j], A[c]);
+        Y[at(h, c, j)] = csel<T>(h, A[c], A[3 + c]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < EH; ++j) {
+        const C back = Y[at(1 - h, c, j)];
+        v[c][j] = csel<T>(h, back, v[c][j]);
+        v[c][j + EH] = csel<T>(h, v[c][j + EH], back);
+      }
+    __syncthreads();                                        // the inverse writes these lines
+  }
+  if (a.mode & XM_INV) {
+    if ((a.mode & XM_FWD) && !(a.mode & (XM_PROJ | XM_DIV | XM_DISP))) __syncthreads();
+    F::template run<T, 3, true, true, true>(v, lds, m, line0, 1, p, d, tw);
+  }
+  const bool store = valid && (h == 0 || !(a.mode & (XM_DIV | XM_DISP)));
+  if (store) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < E; ++i) W[base + c * cstride + (size_t)i * P] = v[c][i];
+  }
+}
+
 // ------------------------------------------------------- launch helper -----
 
 enum KernelKind : int { KK_Z_R2C, KK_Z_C2R, KK_Y_FWD, KK_Y_INV, KK_X, KK_X6, KK_X6S };
@@ -649,6 +745,8 @@ void launch_with(const FastArgs<T>& a) {
       if constexpr (F::ct) {
         if constexpr (F::E % 2 == 0 && F::N / F::E <= 32)
           hipLaunchKernelGGL((k_x6s_r<T, F>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+        else if constexpr (F::E % 2 == 0 && F::N / F::E == 64)
+          hipLaunchKernelGGL((k_x6w_r<T, F>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
       }
       break;
     default:

@@ -20,7 +20,7 @@ template <typename T, int... Rs>
 bool try_sched(const FastArgs<T>& a) {
   using S = Sched<Rs...>;
   if (a.n != S::N || a.E != S::E || !radices_match<Rs...>(a.d)) return false;
-  if (a.kind == KK_X6S && !(S::N / S::E <= 32)) return false;
+  if (a.kind == KK_X6S && !(S::N / S::E <= 32 || S::N / S::E == 64)) return false;
   if (!a.dry) launch_with<T, S>(a);
   return true;
 }
@@ -34,9 +34,12 @@ bool try_sched_x6(const FastArgs<T>& a) {
     if (!a.dry) hipLaunchKernelGGL((k_x6_r<T, S>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
     return true;
   }
-  if constexpr (S::N / S::E <= 32) {
-    if (a.kind == KK_X6S) {
+  if (a.kind == KK_X6S) {
+    if constexpr (S::N / S::E <= 32) {
       if (!a.dry) hipLaunchKernelGGL((k_x6s_r<T, S>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
+      return true;
+    } else if constexpr (S::N / S::E == 64) {
+      if (!a.dry) hipLaunchKernelGGL((k_x6w_r<T, S>), a.grid, a.block, a.lds, a.s, a.W, a.xa, a.d, a.tw, a.sym);
       return true;
     }
   }

@@ -227,7 +227,7 @@ def test_radix4_x_parity(op, shape):
 @pytest.mark.parametrize("shape,radix,P", [((16, 12, 32), {}, 4), ((20, 6, 64), {}, 8), ((8, 10, 128), {}, 16),
                                            ((4, 10, 256), {}, 32), ((6, 18, 96), {}, 4), ((6, 10, 160), {}, 4),
                                            ((4, 6, 192), {}, 8), ((6, 10, 128), {"radix4": 1}, 32),
-                                           ((4, 6, 256), {"radix16": 1}, 16)])
+                                           ((4, 6, 256), {"radix16": 1}, 16), ((4, 6, 512), {}, 64)])
 def test_xsplit_parity(prec, op, shape, radix, P):
     """The x pass split over wavefront halves (three rows per lane, frequencies divided
     between the halves): projection, the spectral divergence of the CDO residual and the
@@ -253,7 +253,7 @@ def test_xsplit_parity(prec, op, shape, radix, P):
         rows = -(-rw * 2 * P // 64) * 64 // (2 * P)
         return 6 * rows * (nx + nx // 16 + 1) * eb <= 65536
 
-    for rw in [r for r in sorted({0, 1, 3, 32 // P}) if r == 0 or lds_ok(r)]:
+    for rw in [r for r in sorted({0, 1, 3, max(1, 32 // P)}) if r == 0 or lds_ok(r)]:
         plan.tune(schedule=5, rw_x=rw, xsplit=2, **radix)
         assert plan.get_tune()["xsplit"] == 2
         x = to_dev(S, prec)
