@@ -402,6 +402,86 @@ def test_residual_norms_definitions():
         assert O.residual_norms(Seq, op, 1.0)[2] <= 1e-14
 
 
+# ------------------------------------------- divergence and its scale ---
+# Section 4.1 (eq:cdo) and Section 4.2 (eq:diff): the residual r_i = sum_j D_j S_ij of a
+# field that is NOT equilibrated, against divergence operators built without the
+# oracle's symbols: the dense cotangent (Fourier) differentiation matrix for CDO and
+# periodic central differences (a dense matrix and np.roll) for DDO.
+
+def _matrix_divergence(S, d1):
+    shape = S.shape[1:]
+    return (divergence_matrix(shape, d1) @ S.ravel()).reshape((3,) + shape)
+
+
+def _divergence_pins_hold(shapes=((8, 6, 10), (4, 4, 4), (6, 8, 4)), h=0.7):
+    """True when oracle.divergence and oracle.residual_norms agree with the matrix
+    operators on random, non-equilibrated fields (both operators)."""
+    for shape in shapes:
+        S = random_field(shape, seed=41 + sum(shape), scale=30.0) + 7.0
+        for op, d1 in (("cdo", lambda n: cotangent_matrix(n, h)), ("ddo", lambda n: central_difference_matrix(n, h))):
+            ref = _matrix_divergence(S, d1)
+            got = O.divergence(S, op, h)
+            if not rel(got, ref) <= 1e-12:
+                return False
+            # the norms: l2, max over voxels of |r|, and rel with the brute-force symbol scale
+            mag2 = np.sum(ref * ref, axis=0)
+            c0 = S.mean(axis=(1, 2, 3))
+            dev = S - c0[:, None, None, None]
+            frob = math.sqrt(float(np.sum(W6[:, None, None, None] * dev * dev)))
+            want = (math.sqrt(float(np.sum(mag2))), math.sqrt(float(mag2.max())),
+                    math.sqrt(float(np.sum(mag2))) / (_brute_symbol_max(op, shape, h) * frob))
+            norms = O.residual_norms(S, op, h)
+            if not all(abs(g - w) <= 1e-12 * abs(w) for g, w in zip(norms, want)):
+                return False
+    return True
+
+
+def _brute_symbol_max(op, shape, h):
+    """max over every frequency q of the full grid of |s(q)|, where s(q) is measured by
+    applying the operator's real-space derivative matrices (cotangent for CDO, central
+    differences for DDO) to the plane wave exp(2 pi i q.x / N): D_j e = i s_j(q) e."""
+    d1 = (lambda n: cotangent_matrix(n, h)) if op == "cdo" else (lambda n: central_difference_matrix(n, h))
+    nz, ny, nx = shape
+    best = 0.0
+    per_axis = []
+    for n in (nx, ny, nz):
+        D = d1(n)
+        x = np.arange(n)
+        vals = []
+        for q in range(n):
+            e = np.exp(2j * math.pi * q * x / n)
+            vals.append(((D @ e) / (1j * e)).real)          # D e = i s e, pointwise
+        per_axis.append(np.array([v[0] for v in vals]))
+    for qz in range(nz):
+        for qy in range(ny):
+            for qx in range(nx):
+                s2 = per_axis[0][qx] ** 2 + per_axis[1][qy] ** 2 + per_axis[2][qz] ** 2
+                best = max(best, s2)
+    return math.sqrt(best)
+
+
+def test_divergence_on_unequilibrated_fields():
+    """oracle.divergence (both branches) and oracle.residual_norms against the matrix
+    divergence operators on random fields that are far from equilibrium."""
+    assert _divergence_pins_hold()
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 6, 10), (6, 8, 4), (12, 4, 6)])
+@pytest.mark.parametrize("op", ["cdo", "ddo"])
+@pytest.mark.parametrize("h", [1.0, 0.37])
+def test_max_symbol_norm_is_the_grid_maximum(op, shape, h):
+    """max_symbol_norm (the scale of the residual's rel) equals the maximum of |s(q)| over
+    the whole grid, with s measured from the real-space operators on plane waves."""
+    assert O.max_symbol_norm(op, shape, h) == pytest.approx(_brute_symbol_max(op, shape, h), rel=1e-12)
+
+
+def test_ddo_divergence_routes_agree_with_roll():
+    """The DDO branch's spectral divergence equals periodic central differences by np.roll
+    on a non-equilibrated field (eq:diff is exactly the DDO symbol)."""
+    S = random_field((6, 10, 8), seed=3, scale=25.0) - 2.0
+    assert rel(O.divergence(S, "ddo", 0.45), O.divergence_central_difference(S, 0.45)) <= 1e-12
+
+
 # ------------------------------------------- potential of the removed part ---
 # Section 3.2: S_exp = S_equil + (grad y + grad y^T)/2.  The oracle's y is a least-squares
 # solve per frequency; the pins check it against that definition in real space.
@@ -563,3 +643,55 @@ def test_planted_nyquist_second_derivative_is_caught(monkeypatch):
 
     monkeypatch.setattr(O.equilibrium, "signed_wavenumber", mutant)
     assert _argmin_fails(monkeypatch, "cdo")
+
+
+def _patch_divergence(monkeypatch, fn):
+    """Replace the oracle's divergence where it is defined and where it is re-exported."""
+    monkeypatch.setattr(O.equilibrium, "divergence", fn)
+    monkeypatch.setattr(O, "divergence", fn)
+
+
+def test_planted_doubled_cdo_divergence_is_caught(monkeypatch):
+    orig = O.equilibrium.divergence
+    _patch_divergence(monkeypatch, lambda S, op, h=1.0: 2.0 * orig(S, op, h) if op == "cdo" else orig(S, op, h))
+    assert not _divergence_pins_hold()
+
+
+def test_planted_divergence_without_i_is_caught(monkeypatch):
+    """The derivative symbol applied without its factor i (a real multiplier)."""
+    def mutant(S, op, h=1.0):
+        S = np.asarray(S, dtype=np.float64)
+        shape = S.shape[1:]
+        F = O.dft3(S)
+        s = O.equilibrium._grid_symbols(op, shape, h, 0, shape[0])
+        M = O.voigt_to_matrix(F)
+        R = np.stack([sum(s[j] * M[i, j] for j in range(3)) for i in range(3)])
+        return O.idft3(R, shape)
+
+    _patch_divergence(monkeypatch, mutant)
+    assert not _divergence_pins_hold()
+
+
+def test_planted_divergence_transposed_index_is_caught(monkeypatch):
+    """r_i = sum_j D_i S_ij (derivative on the wrong index) instead of sum_j D_j S_ij."""
+    def mutant(S, op, h=1.0):
+        S = np.asarray(S, dtype=np.float64)
+        shape = S.shape[1:]
+        F = O.dft3(S)
+        s = O.equilibrium._grid_symbols(op, shape, h, 0, shape[0])
+        M = O.voigt_to_matrix(F)
+        R = np.stack([sum(1j * s[i] * M[i, j] for j in range(3)) for i in range(3)])
+        return O.idft3(R, shape)
+
+    _patch_divergence(monkeypatch, mutant)
+    assert not _divergence_pins_hold()
+
+
+def test_planted_symbol_scale_is_caught(monkeypatch):
+    """max_symbol_norm taken over one axis only (a dropped term) changes rel."""
+    def mutant(op, shape, h):
+        return float(np.max(np.abs(O.axis_symbol(op, shape[-1], h))))
+
+    monkeypatch.setattr(O.equilibrium, "max_symbol_norm", mutant)
+    monkeypatch.setattr(O, "max_symbol_norm", mutant)
+    assert not _divergence_pins_hold()
