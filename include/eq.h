@@ -106,7 +106,7 @@ eq_status eq_project(eq_plan_t p, const void* s_in, void* s_eq, void* s_removed)
  * Blocks until norms_host is written. */
 eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_out);
 
-/* Non-periodic sample in a zero-stress lateral buffer (Section 3.3; Section 6, experimental
+/* Non-periodic sample in a zero-stress lateral buffer (Section 3.3; Section 5.2, experimental
  * sample): the sample (nx0 x ny0 voxels in x and y, all nz planes, so top and bottom are
  * periodically connected) sits at (ox, oy) inside the plan's periodic (nx, ny) box; every
  * other voxel of the box is zero stress.  The box is projected as by eq_project and the

@@ -242,7 +242,7 @@ def project(S: np.ndarray, op: str = "ddo", h: float = 1.0, route: str = "litera
 def embed_in_buffer(S: np.ndarray, box_xy, offset_xy) -> np.ndarray:
     """Place a non-periodic sample (6, nz, ny0, nx0) at (ox, oy) inside a periodic box of
     (nx, ny) voxels laterally, zero stress elsewhere; z keeps its extent, so top and bottom
-    are periodically connected (Section 3.3; Section 6, experimental sample)."""
+    are periodically connected (Section 3.3; Section 5.2, experimental sample)."""
     S = np.asarray(S, dtype=np.float64)
     nx, ny = box_xy
     ox, oy = offset_xy
