@@ -79,7 +79,12 @@ def make_workload(name: str, prec: str):
     return S[None], desc
 
 
-def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tune=True):
+TUNE_FILE = os.path.join(ROOT, "profiles", "tune_mi355x.json")
+
+
+def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tune=True, removed=True):
+    """Time `steps` steps of eq_project (+ eq_residual of the result) on device-resident input.
+    removed=False and with_residual=False time the projection alone (no removed part)."""
     import torch
     import paper_2105_01612_amd as eq
 
@@ -89,14 +94,15 @@ def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tu
         plan = eq.plan(nx, ny, nz, batch=B, op=op, prec=prec)
         x = torch.from_numpy(S_host).to("cuda")
         out = torch.empty_like(x)
-        rem = torch.empty_like(x)
+        rem = torch.empty_like(x) if removed else None
         norms = None
         tuned = None
         if tune:
             from paper_2105_01612_amd.autotune import autotune
 
-            tuned = autotune(plan, x, out, rem, reps=3, use_cache=bool(os.environ.get("EQ_AUTOTUNE_CACHE")))
-            log(f"[bench] autotuned {prec} {op}: {tuned['tune']} -> {tuned['resolved']}")
+            tuned = autotune(plan, x, out, torch.empty_like(x) if rem is None else rem, reps=3,
+                             use_cache=bool(os.environ.get("EQ_AUTOTUNE_CACHE")))
+            log(f"[bench] tuning {prec} {op}: {tuned['tune']} -> {tuned['resolved']}")
         for _ in range(warmup):
             plan.project(x, out, rem)
             if with_residual:
@@ -134,12 +140,26 @@ def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tu
         plan.set_timing(False)
         stats = plan.pass_stats()
         result = out.cpu()
+        rem_host = rem.cpu() if removed else None
+        resolved = plan.get_tune()
         plan.destroy()
     return {"elapsed_s": elapsed, "lat_ms": lat, "stats": stats, "all_stats": all_stats, "out": result,
-            "norms": norms, "tune": tuned["resolved"] if tuned else None}
+            "removed": rem_host, "norms": norms, "tune": resolved}
 
 
 PROJECT_PASSES = ("z_r2c", "y_fwd", "x_proj", "y_inv", "z_c2r", "plane_r2c", "z_proj", "plane_c2r", "div_ddo")
+
+# Algorithmic bytes per voxel of one pass in FP32 (doubled for FP64): one read and one
+# write of the six components (48 B), plus the removed part's write (24 B) on the pass
+# that produces it; the DDO residual reads the field once (24 B).
+SEC8D_BYTES_FP32 = {"z_r2c": 48, "y_fwd": 48, "x_proj": 48, "y_inv": 48, "z_c2r": 48, "plane_r2c": 48,
+                    "z_proj": 48, "plane_c2r": 48, "div_ddo": 24}
+REMOVED_PASSES = ("z_c2r", "plane_c2r")
+
+
+def sec8d_bytes(name, voxels, prec, removed):
+    b = SEC8D_BYTES_FP32.get(name, 0) + (24 if removed and name in REMOVED_PASSES else 0)
+    return b * voxels * (2 if prec == "fp64" else 1)
 
 
 def slowest_pass(stats):
@@ -153,9 +173,12 @@ def slowest_pass(stats):
     return best[0] if best else None
 
 
-def roofline(stats, all_stats, workload):
-    """The slowest kernel's rate from the timed region's events; the per-pass table from
-    the fully instrumented steps before it."""
+def roofline(stats, all_stats, workload, voxels, prec="fp32", removed=True):
+    """The slowest kernel's rate from the timed region's events, on the algorithmic bytes per
+    voxel of one pass (48 B FP32, + 24 B for the removed part's write, 24 B for the DDO
+    residual); the bytes that pass actually moves (its own reads of the input for the removed
+    part included) are reported beside it.  The per-pass table comes from the fully
+    instrumented steps before the timed region."""
     best = None
     for name in PROJECT_PASSES:
         st = stats.get(name)
@@ -167,7 +190,8 @@ def roofline(stats, all_stats, workload):
     if best is None:
         return None, {}
     name, avg_ms, by = best
-    achieved = by / (avg_ms * 1e-3) / 1e9
+    alg = sec8d_bytes(name, voxels, prec, removed)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
     per_pass = {}
     for n, st in (all_stats or stats).items():
         if st["launches"]:
@@ -176,7 +200,10 @@ def roofline(stats, all_stats, workload):
                            "launches": st["launches"]}
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5),
-            "bytes_per_launch": by, "traffic": load_traffic(name, workload)}, per_pass
+            "algorithmic_bytes_per_launch": alg, "algorithmic_bytes_per_voxel": alg / voxels,
+            "pass_bytes_per_launch": by, "pass_bytes_per_voxel": round(by / voxels, 2),
+            "pass_frac": round(by / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic(name, workload)}, per_pass
 
 
 def frob_err(got, ref):
@@ -195,23 +222,53 @@ def roundoff_amplification(S, S_eq):
     return math.sqrt(num / den) if den > 0 else None
 
 
+def batched_errors(S32, out, op):
+    """The oracle error of every field of a batch (FP32 result against the FP64 oracle on the
+    same input bytes): max and median rel-L2 and the largest max-abs."""
+    import oracle
+
+    os.environ["ORACLE_WORKERS"] = str(os.cpu_count() or 1)
+    t = time.perf_counter()
+    rel, mab = [], []
+    for b in range(S32.shape[0]):
+        ref, _ = oracle.project(S32[b].astype(np.float64), op)
+        e = frob_err(out[b:b + 1], ref[None])
+        rel.append(e[0])
+        mab.append(e[1])
+    log(f"[bench] oracle error of {len(rel)} fields in {time.perf_counter() - t:.1f} s: max rel-L2 {max(rel):.2e}")
+    return {"fields": len(rel), "rel_l2_max": max(rel), "rel_l2_median": float(np.median(rel)),
+            "max_abs_mpa": max(mab), "tol": 1e-5}
+
+
 def cpu_baseline(S_field64, op):
     """The FP64 oracle on the host, on one whole field (the bounded sample)."""
     import oracle
 
-    cores = min(os.cpu_count() or 1, int(os.environ.get("BENCH_ORACLE_CORES", "16")))
-    os.environ["ORACLE_WORKERS"] = str(cores)
-    # repeat the whole-field projection until about 10 s of host work (at most 5 runs)
-    runs, dt = 0, 0.0
-    while runs < 5 and (runs == 0 or dt < 10.0):
-        t0 = time.perf_counter()
-        ref, _ = oracle.project(S_field64, op)
-        dt += time.perf_counter() - t0
-        runs += 1
+    cores = os.cpu_count() or 1
     vox = S_field64[0].size
+    grid = "x".join(map(str, S_field64.shape[1:][::-1]))
+
+    def timed(workers, max_runs, budget_s):
+        os.environ["ORACLE_WORKERS"] = str(workers)
+        runs, dt, ref = 0, 0.0, None
+        while runs < max_runs and (runs == 0 or dt < budget_s):
+            t0 = time.perf_counter()
+            ref, _ = oracle.project(S_field64, op)
+            dt += time.perf_counter() - t0
+            runs += 1
+        return ref, runs, dt
+
+    # all host cores (scipy.fft workers = os.cpu_count()), repeated to about 10 s; then one core
+    ref, runs, dt = timed(cores, 5, 10.0)
+    _, runs1, dt1 = timed(1, 1, 0.0)
+    log(f"[bench] oracle host: os.cpu_count() = {cores}; {runs} runs in {dt:.2f} s with {cores} workers, "
+        f"{dt1:.2f} s with 1")
     return ref, {"value": vox * runs / dt, "unit": "voxels/s", "cores": cores, "kind": "oracle",
-                 "sample": f"{runs} x one whole field ({'x'.join(map(str, S_field64.shape[1:][::-1]))}), FP64, "
-                           f"{op.upper()}, numpy + scipy.fft with {cores} workers, {dt:.2f} s in total"}
+                 "sample": f"{runs} x one whole field ({grid}), FP64, {op.upper()}, numpy + scipy.fft with "
+                           f"workers = os.cpu_count() = {cores}, {dt:.2f} s in total",
+                 "single_core": {"value": vox * runs1 / dt1, "unit": "voxels/s", "cores": 1,
+                                 "sample": f"{runs1} x one whole field ({grid}), scipy.fft workers = 1, "
+                                           f"{dt1:.2f} s"}}
 
 
 def run_serve(args):
@@ -395,7 +452,7 @@ def main():
                   tune=not args.no_autotune)
     ms32 = r32["elapsed_s"] / args.steps * 1e3
     log(f"[bench] fp32 {args.op}: {ms32:.3f} ms/step")
-    roof, per_pass = roofline(r32["stats"], r32["all_stats"], args.workload)
+    roof, per_pass = roofline(r32["stats"], r32["all_stats"], args.workload, vox, "fp32", removed=True)
 
     line = {
         "metric": METRIC,
@@ -424,6 +481,8 @@ def main():
         "hbm_frac_compulsory_48B": (vox / r32["elapsed_s"] * args.steps) * 48 / (HBM_PEAK_GBS * 1e9),
         "residual_of_output": r32["norms"][0] if r32["norms"] else None,
         "tune": r32["tune"],
+        "tune_source": os.environ.get("EQ_AUTOTUNE_CACHE") or ("autotuned in this run" if not args.no_autotune
+                                                                 else "library defaults"),
         "paper_context": PAPER_CONTEXT,
     }
     if r32["all_stats"]:
@@ -432,6 +491,18 @@ def main():
         line["step_bytes_per_voxel"] = round(step_bytes / vox, 2)
         line["hbm_frac_step_bytes"] = step_bytes / (ms32 * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
+    if not args.no_compare:
+        # the projection alone (no removed part, no residual): 144 B/voxel is its three-pass minimum
+        rp = run_gpu(S32, args.op, "fp32", args.steps, 2, with_residual=False, timing=False,
+                     tune=not args.no_autotune, removed=False)
+        msp = rp["elapsed_s"] / args.steps * 1e3
+        log(f"[bench] fp32 {args.op} projection only: {msp:.3f} ms")
+        line["project_only"] = {"ms": msp, "value": vox / (msp * 1e-3), "unit": "voxels/s",
+                                "hbm_frac_144B_schedule_min": vox / (msp * 1e-3) * 144 / (HBM_PEAK_GBS * 1e9),
+                                "tune": rp["tune"]}
+        del rp
+    if args.workload == "batched" and not args.no_cpu_baseline:
+        line["error_vs_oracle"] = batched_errors(S32, r32["out"].numpy(), args.op)
     if not args.no_compare and args.workload != "batched":
         S64 = S32.astype(np.float64)
         r64 = run_gpu(S64, args.op, "fp64", max(3, args.steps // 2), 2, timing=False, tune=not args.no_autotune)
@@ -453,6 +524,14 @@ def main():
                                        "fp64": {"rel_l2": e64[0], "max_abs_mpa": e64[1], "tol": 1e-12},
                                        "roundoff_amplification": roundoff_amplification(S64[0], ref)}
             log(f"[bench] oracle {cb['sample']}; fp32 rel-L2 {e32[0]:.2e}, fp64 rel-L2 {e64[0]:.2e}")
+            # the other operator's FP32 result against its own oracle
+            import oracle
+
+            os.environ["ORACLE_WORKERS"] = str(os.cpu_count() or 1)
+            ref_o, _ = oracle.project(S64[0], other)
+            eo = frob_err(rc["out"].numpy()[:1], ref_o[None])
+            line[f"{other}_fp32"]["error_vs_oracle"] = {"rel_l2": eo[0], "max_abs_mpa": eo[1], "tol": 1e-5}
+            log(f"[bench] {other} fp32 rel-L2 {eo[0]:.2e}")
     print(json.dumps(line), flush=True)
 
 

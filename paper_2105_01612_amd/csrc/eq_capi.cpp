@@ -594,6 +594,8 @@ eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out
   const double w[6] = {1, 1, 1, 2, 2, 2};
   for (int b = 0; b < g.batch; ++b) {
     const double* r = &host[(size_t)b * kRedWidth];
+    // ||S - c0||_F^2 from sums of d = S - shift (shift: the field's first voxel), so a mean
+    // far above the spread does not cancel
     double dev2 = 0.0;
     for (int c = 0; c < 6; ++c) dev2 += w[c] * (r[8 + c] - r[2 + c] * r[2 + c] / (double)M);
     const double l2 = std::sqrt(r[0]);
@@ -626,7 +628,10 @@ struct DeviceGuard {
 extern "C" {
 
 const char* eq_status_str(eq_status s) {
-  switch (s) {
+  // C callers may pass any int; read it as one (a C++ load of an out-of-range enum value is undefined)
+  int v = 0;
+  std::memcpy(&v, &s, sizeof(v) < sizeof(s) ? sizeof(v) : sizeof(s));
+  switch (v) {
     case EQ_OK: return "EQ_OK";
     case EQ_ERR_ARG: return "EQ_ERR_ARG";
     case EQ_ERR_SIZE: return "EQ_ERR_SIZE";

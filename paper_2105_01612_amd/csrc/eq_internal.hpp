@@ -82,7 +82,7 @@ hipError_t launch_z_c2r(const cplx<T>* W, T* out, size_t out_field, size_t out_c
                         hipStream_t s, const Embed& e = Embed{});
 
 // Reduction record per field (kRedWidth doubles):
-//   [0] sum_x |r|^2, [1] max_x |r|^2, [2..7] sum_x S_c, [8..13] sum_x S_c^2
+//   [0] sum_x |r|^2, [1] max_x |r|^2, [2..7] sum_x d_c, [8..13] sum_x d_c^2 with d_c = S_c - S_c(first voxel)
 constexpr int kRedWidth = 14;
 
 // DDO residual; nblk_max bounds the workgroups per field (partials holds batch * nblk_max

@@ -235,6 +235,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_x_g(cplx<T>* __restrict__ W, XA
 
 constexpr int kRedThreads = 256;
 
+// A value every lane holds alike, moved to scalar registers (exact: lane 0's copy).
+__device__ __forceinline__ double uniform_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Deterministic block reduction of the kRedWidth record (sums, except [1] = max).
 __device__ __forceinline__ void block_reduce_record(double* v, double* sh /* kRedWidth * kRedThreads */) {
   const int t = threadIdx.x;
@@ -278,6 +286,22 @@ struct FieldReader {
       if constexpr (BUF) r[c] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f[c]), 0, (int)(M * sizeof(T)), kBufWord3);
     }
   }
+  // the stored value, unconverted
+  __device__ __forceinline__ T raw(int c, size_t e) const {
+    if constexpr (BUF) {
+      const unsigned off = (unsigned)e * (unsigned)sizeof(T);
+      if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r[c], off, 0, 0));
+      } else {
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b64(r[c], off, 0, 0);
+        double v;
+        __builtin_memcpy(&v, &raw, sizeof(v));
+        return v;
+      }
+    } else {
+      return f[c][e];
+    }
+  }
   __device__ __forceinline__ double operator()(int c, size_t e) const {
     if constexpr (BUF) {
       const unsigned off = (unsigned)e * (unsigned)sizeof(T);
@@ -311,6 +335,11 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
   double acc[kRedWidth];
 #pragma unroll
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+  // the component sums are taken about the field's first voxel, so the variance of a field
+  // whose mean is large against its spread does not cancel (sum d^2 - (sum d)^2 / M, d = S - shift);
+  // the shifts are the same in every lane and are kept in scalar registers
+  const double sh0 = uniform_f64(F(0, 0)), sh1 = uniform_f64(F(1, 0)), sh2 = uniform_f64(F(2, 0));
+  const double sh3 = uniform_f64(F(3, 0)), sh4 = uniform_f64(F(4, 0)), sh5 = uniform_f64(F(5, 0));
   const int lx = threadIdx.x % a.tx, ly = threadIdx.x / a.tx;
   const int items = a.tiles * a.zc;
   // each XCD takes a contiguous run of work items, so the y-halo rows of neighbouring
@@ -334,35 +363,67 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
     double a2c = F(2, p0 + ca), a3c = F(3, p0 + ca), a4c = F(4, p0 + ca);
     double b2m = F(2, pm + cb), b3m = F(3, pm + cb), b4m = F(4, pm + cb);
     double b2c = F(2, p0 + cb), b3c = F(3, p0 + cb), b4c = F(4, p0 + cb);
-    for (int z = z0; z < z1; ++z) {
+    // the 30 values one plane step reads (rows a = y, b = y + 1): centres of S11, S22, S12;
+    // x neighbours of S11, S12, S13; the outer y rows of S12, S22, S23; the next plane of S33,
+    // S23, S13.  FP32 fields load the step after next while the current one is evaluated.
+    auto load_step = [&](int z, T* v) {
       const size_t p = (size_t)z * sz;
       const size_t pn = (size_t)(z + 1 == a.nz ? 0 : z + 1) * sz;
-      const double a2p = F(2, pn + ca), a3p = F(3, pn + ca), a4p = F(4, pn + ca);
-      const double b2p = F(2, pn + cb), b3p = F(3, pn + cb), b4p = F(4, pn + cb);
-      const double a0 = F(0, p + ca), a1 = F(1, p + ca), a5 = F(5, p + ca);
-      const double b0 = F(0, p + cb), b1 = F(1, p + cb), b5 = F(5, p + cb);
       const size_t qa = p + ca, qb = p + cb;
+      v[0] = F.raw(0, qa); v[1] = F.raw(1, qa); v[2] = F.raw(5, qa);
+      v[3] = F.raw(0, qb); v[4] = F.raw(1, qb); v[5] = F.raw(5, qb);
+      v[6] = F.raw(0, qa + dxp); v[7] = F.raw(0, qa + dxm); v[8] = F.raw(5, qa + dxp); v[9] = F.raw(5, qa + dxm);
+      v[10] = F.raw(4, qa + dxp); v[11] = F.raw(4, qa + dxm);
+      v[12] = F.raw(0, qb + dxp); v[13] = F.raw(0, qb + dxm); v[14] = F.raw(5, qb + dxp); v[15] = F.raw(5, qb + dxm);
+      v[16] = F.raw(4, qb + dxp); v[17] = F.raw(4, qb + dxm);
+      v[18] = F.raw(5, p + ym); v[19] = F.raw(1, p + ym); v[20] = F.raw(3, p + ym);
+      v[21] = F.raw(5, p + yq); v[22] = F.raw(1, p + yq); v[23] = F.raw(3, p + yq);
+      v[24] = F.raw(2, pn + ca); v[25] = F.raw(3, pn + ca); v[26] = F.raw(4, pn + ca);
+      v[27] = F.raw(2, pn + cb); v[28] = F.raw(3, pn + cb); v[29] = F.raw(4, pn + cb);
+    };
+    constexpr bool kAhead = sizeof(T) == 4;     // FP64 values would take twice the registers
+    T cur[30], nxt[30];
+    load_step(z0, cur);
+    for (int z = z0; z < z1; ++z) {
+      const size_t p = (size_t)z * sz;
+      if (kAhead) {
+        if (z + 1 < z1) load_step(z + 1, nxt);
+      } else if (z > z0) {
+        load_step(z, cur);
+      }
+      const double a0 = cur[0], a1 = cur[1], a5 = cur[2], b0 = cur[3], b1 = cur[4], b5 = cur[5];
+      const double a2p = cur[24], a3p = cur[25], a4p = cur[26], b2p = cur[27], b3p = cur[28], b4p = cur[29];
+      const size_t qa = p + ca;
       // r_x = d_x S11 + d_y S12 + d_z S13, etc. (slots 0=11 1=22 2=33 3=23 4=13 5=12)
-      const double ra0 = ((F(0, qa + dxp) - F(0, qa + dxm)) + (b5 - F(5, p + ym)) + (a4p - a4m)) * a.inv2h;
-      const double ra1 = ((F(5, qa + dxp) - F(5, qa + dxm)) + (b1 - F(1, p + ym)) + (a3p - a3m)) * a.inv2h;
-      const double ra2 = ((F(4, qa + dxp) - F(4, qa + dxm)) + (b3c - F(3, p + ym)) + (a2p - a2m)) * a.inv2h;
-      const double rb0 = ((F(0, qb + dxp) - F(0, qb + dxm)) + (F(5, p + yq) - a5) + (b4p - b4m)) * a.inv2h;
-      const double rb1 = ((F(5, qb + dxp) - F(5, qb + dxm)) + (F(1, p + yq) - a1) + (b3p - b3m)) * a.inv2h;
-      const double rb2 = ((F(4, qb + dxp) - F(4, qb + dxm)) + (F(3, p + yq) - a3c) + (b2p - b2m)) * a.inv2h;
+      const double ra0 = (((double)cur[6] - (double)cur[7]) + (b5 - (double)cur[18]) + (a4p - a4m)) * a.inv2h;
+      const double ra1 = (((double)cur[8] - (double)cur[9]) + (b1 - (double)cur[19]) + (a3p - a3m)) * a.inv2h;
+      const double ra2 = (((double)cur[10] - (double)cur[11]) + (b3c - (double)cur[20]) + (a2p - a2m)) * a.inv2h;
+      const double rb0 = (((double)cur[12] - (double)cur[13]) + ((double)cur[21] - a5) + (b4p - b4m)) * a.inv2h;
+      const double rb1 = (((double)cur[14] - (double)cur[15]) + ((double)cur[22] - a1) + (b3p - b3m)) * a.inv2h;
+      const double rb2 = (((double)cur[16] - (double)cur[17]) + ((double)cur[23] - a3c) + (b2p - b2m)) * a.inv2h;
       const double ma = ra0 * ra0 + ra1 * ra1 + ra2 * ra2;
       const double mb = rb0 * rb0 + rb1 * rb1 + rb2 * rb2;
       acc[0] += ma + mb;
       acc[1] = fmax(acc[1], fmax(ma, mb));
-      acc[2] += a0 + b0; acc[8] += a0 * a0 + b0 * b0;
-      acc[3] += a1 + b1; acc[9] += a1 * a1 + b1 * b1;
-      acc[4] += a2c + b2c; acc[10] += a2c * a2c + b2c * b2c;
-      acc[5] += a3c + b3c; acc[11] += a3c * a3c + b3c * b3c;
-      acc[6] += a4c + b4c; acc[12] += a4c * a4c + b4c * b4c;
-      acc[7] += a5 + b5; acc[13] += a5 * a5 + b5 * b5;
+      {
+        const double d0 = a0 - sh0, e0 = b0 - sh0, d1 = a1 - sh1, e1 = b1 - sh1;
+        const double d2 = a2c - sh2, e2 = b2c - sh2, d3 = a3c - sh3, e3 = b3c - sh3;
+        const double d4 = a4c - sh4, e4 = b4c - sh4, d5 = a5 - sh5, e5 = b5 - sh5;
+        acc[2] += d0 + e0; acc[8] += d0 * d0 + e0 * e0;
+        acc[3] += d1 + e1; acc[9] += d1 * d1 + e1 * e1;
+        acc[4] += d2 + e2; acc[10] += d2 * d2 + e2 * e2;
+        acc[5] += d3 + e3; acc[11] += d3 * d3 + e3 * e3;
+        acc[6] += d4 + e4; acc[12] += d4 * d4 + e4 * e4;
+        acc[7] += d5 + e5; acc[13] += d5 * d5 + e5 * e5;
+      }
       if (div) {
         T* o = div + (size_t)b * 3 * M + qa;
         o[0] = (T)ra0; o[M] = (T)ra1; o[2 * M] = (T)ra2;
         o[a.nx] = (T)rb0; o[M + a.nx] = (T)rb1; o[2 * M + a.nx] = (T)rb2;
+      }
+      if (kAhead) {
+#pragma unroll
+        for (int k = 0; k < 30; ++k) cur[k] = nxt[k];
       }
       a2m = a2c; a3m = a3c; a4m = a4c;
       a2c = a2p; a3c = a3p; a4c = a4p;
@@ -394,6 +455,9 @@ __global__ __launch_bounds__(kRedThreads) void k_div_stats(const T* __restrict__
   double acc[kRedWidth];
 #pragma unroll
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+  double shift[6];                       // sums about the field's first voxel (see k_div_ddo)
+#pragma unroll
+  for (int c = 0; c < 6; ++c) shift[c] = uniform_f64((double)F[c * M]);
   for (size_t v = (size_t)blockIdx.x * kRedThreads + threadIdx.x; v < M; v += (size_t)gridDim.x * kRedThreads) {
     const double r0 = R[v], r1 = R[a.div_comp + v], r2 = R[2 * a.div_comp + v];
     const double m2 = r0 * r0 + r1 * r1 + r2 * r2;
@@ -401,7 +465,7 @@ __global__ __launch_bounds__(kRedThreads) void k_div_stats(const T* __restrict__
     acc[1] = fmax(acc[1], m2);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      const double s = (double)F[c * M + v];
+      const double s = (double)F[c * M + v] - shift[c];
       acc[2 + c] += s;
       acc[8 + c] += s * s;
     }

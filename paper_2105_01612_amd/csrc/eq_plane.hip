@@ -12,9 +12,9 @@
 //
 // Each pass reads and writes the field or its half spectrum once, so the projection
 // moves three round trips of HBM instead of five.  The forward and inverse DFTs are
-// the unnormalized analysis/synthesis pair of Section 3 (eqnFFT/eqniFFT, with the
+// the unnormalized analysis/synthesis pair of Section 4 (eqnFFT/eqniFFT, with the
 // 1/N^3 on the synthesis side); the per-frequency projection is Theorem 2 in the
-// P A P form (Section 3, eq:sequil with the gauge of eqnELH).
+// P A P form (Section 3.2, eq:sequil with the gauge of eqnELH).
 //
 // Real-to-complex along x packs rows 2j and 2j+1 of a plane into one complex line,
 // z = a + i b, and separates the two half spectra from Z(k) and Z(n - k).  Columns

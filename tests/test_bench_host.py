@@ -29,12 +29,19 @@ def test_slowest_pass_ignores_non_projection_kernels():
 def test_roofline_arithmetic():
     timed = stats(z_c2r=0.25)                       # only the slowest kernel bracketed
     table = stats(z_r2c=0.125, z_c2r=0.25)          # every kernel, earlier steps
-    roof, per_pass = bench.roofline(timed, table, "no_such_workload")
+    vox = 256 ** 3
+    roof, per_pass = bench.roofline(timed, table, "no_such_workload", vox, "fp32", removed=True)
     assert roof["kernel"] == "z_c2r" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
-    assert roof["achieved"] == pytest.approx(4000.0)          # 1 GB in 0.25 ms
+    # algorithmic bytes of the pass that writes the removed part: 48 + 24 B per voxel
+    assert roof["algorithmic_bytes_per_voxel"] == 72
+    assert roof["achieved"] == pytest.approx(72 * vox / 0.25e-3 / 1e9, rel=1e-6)
     assert roof["peak"] == bench.HBM_PEAK_GBS
-    assert roof["frac"] == pytest.approx(0.5)
+    assert roof["frac"] == pytest.approx(roof["achieved"] / bench.HBM_PEAK_GBS, rel=1e-3)
+    # the pass's own bytes (the event records' 1 GB) are reported beside it
+    assert roof["pass_bytes_per_launch"] == 1e9 and roof["pass_frac"] == pytest.approx(0.5)
     assert roof["traffic"] is None                             # no counter record for this workload
+    roof64, _ = bench.roofline(timed, table, "no_such_workload", vox, "fp64", removed=False)
+    assert roof64["algorithmic_bytes_per_voxel"] == 96
     assert set(per_pass) == {"z_r2c", "z_c2r"}
     assert per_pass["z_r2c"]["GB_s"] == pytest.approx(8000.0)
 
