@@ -34,7 +34,7 @@ def test_roofline_arithmetic():
     assert roof["kernel"] == "z_c2r" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
     # algorithmic bytes of the pass that writes the removed part: 48 + 24 B per voxel
     assert roof["algorithmic_bytes_per_voxel"] == 72
-    assert roof["achieved"] == pytest.approx(72 * vox / 0.25e-3 / 1e9, rel=1e-6)
+    assert roof["achieved"] == pytest.approx(72 * vox / 0.25e-3 / 1e9, rel=1e-4)
     assert roof["peak"] == bench.HBM_PEAK_GBS
     assert roof["frac"] == pytest.approx(roof["achieved"] / bench.HBM_PEAK_GBS, rel=1e-3)
     # the pass's own bytes (the event records' 1 GB) are reported beside it
