@@ -106,6 +106,23 @@ eq_status eq_project(eq_plan_t p, const void* s_in, void* s_eq, void* s_removed)
  * Blocks until norms_host is written. */
 eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_out);
 
+/* eq_residual without any allocation, for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * No plan: *d describes the fields (its flags are ignored) and the call enqueues the DDO
+ * stencil and the final reduction on hip_stream (NULL = the null stream) of the current
+ * device.  The per-workgroup partial sums live in a static device array of the library
+ * (7.3 MB per device, held until the process ends), so at most 64 fields per call.
+ *   d         : as for eq_plan; op must be EQ_OP_DDO (the CDO residual needs a plan's
+ *               spectrum workspace) else EQ_ERR_ARG; batch > 64 -> EQ_ERR_SIZE;
+ *   s         : device (batch, 6, nz, ny, nx), element type per d->prec;
+ *   norms_dev : DEVICE double [batch][3] = { l2, max, rel } as eq_residual's norms_host;
+ *   div_out   : nullable, DEVICE (batch, 3, nz, ny, nx) of the element type.
+ * Stream-ordered and asynchronous (nothing is copied to the host).  Every call on one
+ * device shares the array: calls that overlap in time on one device race, so serialize
+ * them (one stream, or events).  Values equal eq_residual's to rounding of the final
+ * division and square roots, which here run on the device. */
+eq_status eq_residual_noalloc(const eq_desc* d, void* hip_stream, const void* s, double* norms_dev, void* div_out);
+
 /* Non-periodic sample in a zero-stress lateral buffer (Section 3.3; Section 5.2, experimental
  * sample): the sample (nx0 x ny0 voxels in x and y, all nz planes, so top and bottom are
  * periodically connected) sits at (ox, oy) inside the plan's periodic (nx, ny) box; every

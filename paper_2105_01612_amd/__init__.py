@@ -19,7 +19,7 @@ import os
 from typing import Dict, List, Optional, Tuple
 
 __all__ = ["EqError", "Plan", "plan", "footprint", "lib", "library_path", "OP", "PREC", "FLAGS",
-           "STATUS", "version", "exported_symbols"]
+           "STATUS", "version", "exported_symbols", "residual_noalloc"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libeq.so")
@@ -35,7 +35,7 @@ exported_symbols = (
     "eq_plan", "eq_project", "eq_residual", "eq_plan_destroy", "eq_plan_footprint", "eq_status_str",
     "eq_last_error", "eq_plan_set_stream", "eq_plan_set_timing", "eq_plan_pass_stats",
     "eq_plan_reset_stats", "eq_debug_forward", "eq_debug_project_spectrum", "eq_version", "eq_plan_tune",
-    "eq_plan_get_tune", "eq_potential", "eq_project_embedded", "eq_plan_set_timing_pass",
+    "eq_plan_get_tune", "eq_potential", "eq_project_embedded", "eq_plan_set_timing_pass", "eq_residual_noalloc",
 )
 
 
@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
     L.eq_project.argtypes = [vp, vp, vp, vp]
     L.eq_residual.argtypes = [vp, vp, dp, vp]
     L.eq_potential.argtypes = [vp, vp, vp]
+    L.eq_residual_noalloc.argtypes = [ctypes.POINTER(EqDesc), vp, vp, vp, vp]
     L.eq_project_embedded.argtypes = [vp, ctypes.POINTER(EqEmbed), vp, vp, vp]
     L.eq_plan_destroy.argtypes = [vp]
     L.eq_plan_footprint.argtypes = [ctypes.POINTER(EqDesc), ctypes.POINTER(ctypes.c_size_t)]
@@ -319,6 +320,33 @@ class Plan:
 
     def __exit__(self, *exc):
         self.destroy()
+
+
+def residual_noalloc(s, norms_dev, nx, ny=None, nz=None, batch=1, prec="fp64", h=1.0, div_out=None, stream=None):
+    """eq_residual_noalloc: the DDO residual of `s` without any allocation (no plan); the norms
+    (l2, max, rel) per field go to the device tensor `norms_dev` (batch, 3) of float64,
+    asynchronously on `stream` (None: torch's current stream)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    d = _desc(nx, ny, nz, batch, "ddo", prec, h, 0)
+    import torch
+
+    dt = torch.float64 if d.prec == 0 else torch.float32
+    for t, name in ((s, "s"), (div_out, "div_out")):
+        if t is not None and (not t.is_cuda or t.dtype != dt or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous device tensor of {dt}")
+    if s.numel() != batch * 6 * nx * ny * nz:
+        raise ValueError("s does not hold batch * 6 * nz * ny * nx elements")
+    if div_out is not None and div_out.numel() != batch * 3 * nx * ny * nz:
+        raise ValueError("div_out does not hold batch * 3 * nz * ny * nx elements")
+    if (not norms_dev.is_cuda or norms_dev.dtype != torch.float64 or not norms_dev.is_contiguous()
+            or norms_dev.numel() < 3 * batch):
+        raise ValueError("norms_dev must be a contiguous float64 device tensor of batch * 3 elements")
+    handle = _stream_handle(stream)
+    _check(lib().eq_residual_noalloc(ctypes.byref(d), ctypes.c_void_p(handle) if handle else None, s.data_ptr(),
+                                     norms_dev.data_ptr(), div_out.data_ptr() if div_out is not None else None),
+           "eq_residual_noalloc")
+    return norms_dev
 
 
 def plan(nx, ny=None, nz=None, batch=1, op="ddo", prec="fp64", h=1.0, flags=0, stream="current") -> Plan:

@@ -163,7 +163,6 @@ double symbol_max2(const eq_desc* d) {
   return smax2;
 }
 
-constexpr int kRedBlocks = 1024;  // reduction partial records per field (upper bound on workgroups)
 
 struct Layout {
   size_t w_bytes, sym_bytes, tw64_bytes, tw32_bytes, part_bytes, red_bytes, flag_bytes;
@@ -794,6 +793,45 @@ eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_
   DeviceGuard dg(p->device);
   return p->desc.prec == EQ_FP64 ? run_residual<double>(p, s, norms_host, div_out)
                                  : run_residual<float>(p, s, norms_host, div_out);
+}
+
+eq_status eq_residual_noalloc(const eq_desc* d, void* hip_stream, const void* s, double* norms_dev, void* div_out) {
+  eq_status st = validate(d);
+  if (st != EQ_OK) return st;
+  if (d->op != EQ_OP_DDO)
+    return fail(EQ_ERR_ARG, "eq_residual_noalloc: DDO operator only (the CDO residual needs a plan's spectrum workspace)");
+  if (!s || !norms_dev) return fail(EQ_ERR_ARG, "null field or norms pointer");
+  if (d->batch > kNoAllocFields)
+    return fail(EQ_ERR_SIZE, "eq_residual_noalloc: batch " + std::to_string(d->batch) + " exceeds the maximum of " +
+                                 std::to_string(kNoAllocFields) + " fields of its static scratch");
+  const size_t es = elem_size(d);
+  const size_t M = (size_t)d->nx * d->ny * d->nz;
+  const size_t bytes = (size_t)d->batch * 6 * M * es;
+  const uintptr_t xs = (uintptr_t)s;
+  auto hits_field = [&](const void* q, size_t qbytes) {
+    const uintptr_t xq = (uintptr_t)q;
+    return xq < xs + bytes && xs < xq + qbytes;
+  };
+  if (div_out && hits_field(div_out, (size_t)d->batch * 3 * M * es)) return fail(EQ_ERR_ARG, "div_out overlaps the field");
+  if (hits_field(norms_dev, (size_t)d->batch * 3 * sizeof(double))) return fail(EQ_ERR_ARG, "norms_dev overlaps the field");
+  const Geom g{d->nx, d->ny, d->nz, d->nz / 2 + 1, d->batch};
+  double* scr = nullptr;
+  EQ_HIP(noalloc_scratch(&scr), "hipGetSymbolAddress(scratch)");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const bool fp64 = d->prec == EQ_FP64;
+  if (fp64) {
+    EQ_HIP(launch_div_ddo<double>(static_cast<const double*>(s), static_cast<double*>(div_out), scr, kRedBlocks, g,
+                                  d->h, stream),
+           "div_ddo launch");
+  } else {
+    EQ_HIP(launch_div_ddo<float>(static_cast<const float*>(s), static_cast<float*>(div_out), scr, kRedBlocks, g, d->h,
+                                 stream),
+           "div_ddo launch");
+  }
+  const int nred = div_ddo_blocks(g, kRedBlocks, fp64);
+  EQ_HIP(launch_reduce_norms(scr, nred, d->batch, 1.0 / (double)M, std::sqrt(symbol_max2(d)), norms_dev, stream),
+         "reduce launch");
+  return EQ_OK;
 }
 
 eq_status eq_potential(eq_plan_t p, const void* s_in, void* y_out) {

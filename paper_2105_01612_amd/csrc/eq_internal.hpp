@@ -98,6 +98,17 @@ hipError_t launch_div_stats(const T* div, size_t div_field, size_t div_comp, con
 
 hipError_t launch_reduce_final(const double* partials, int nblk, int batch, double* out, hipStream_t s);
 
+// Partial records per field (an upper bound on the residual's workgroups per field).
+constexpr int kRedBlocks = 1024;
+// Allocation-free residual: at most kNoAllocFields fields per call; its partial records live
+// in a static device array whose address noalloc_scratch returns for the current device.
+constexpr int kNoAllocFields = 64;
+hipError_t noalloc_scratch(double** out);
+// The final reduction finished on the device: norms[b] = (l2, max, rel), inv_m = 1 / voxels
+// per field, smax = max_q |s(q)|.
+hipError_t launch_reduce_norms(const double* partials, int nblk, int batch, double inv_m, double smax, double* norms,
+                               hipStream_t s);
+
 template <typename T>
 hipError_t launch_check_finite(const T* in, size_t n, int* flag, hipStream_t s);
 

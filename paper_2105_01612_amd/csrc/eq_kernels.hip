@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
 
 #include "eq_fft.hpp"
 #include "eq_internal.hpp"
@@ -478,11 +479,9 @@ __global__ __launch_bounds__(kRedThreads) void k_div_stats(const T* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ partials, int nblk,
-                                                              double* __restrict__ out) {
-  __shared__ double sh[kRedWidth * kRedThreads];
-  const int b = blockIdx.x;
-  double acc[kRedWidth];
+// Field b's record from its nblk partial records (same order whatever the caller).
+__device__ __forceinline__ void reduce_field_record(const double* __restrict__ partials, int nblk, int b,
+                                                    double* acc, double* sh) {
 #pragma unroll
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
   for (int i = threadIdx.x; i < nblk; i += kRedThreads) {
@@ -491,11 +490,46 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __re
     for (int k = 0; k < kRedWidth; ++k) acc[k] = (k == 1) ? fmax(acc[k], pp[k]) : acc[k] + pp[k];
   }
   block_reduce_record(acc, sh);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ partials, int nblk,
+                                                              double* __restrict__ out) {
+  __shared__ double sh[kRedWidth * kRedThreads];
+  const int b = blockIdx.x;
+  double acc[kRedWidth];
+  reduce_field_record(partials, nblk, b, acc, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < kRedWidth; ++k) out[(size_t)b * kRedWidth + k] = acc[k];
   }
 }
+
+// The same reduction, finished on the device: norms[b] = (l2, max, rel) with
+// rel = l2 / (smax * ||S - c0||_F), ||S - c0||_F^2 = sum_c w_c (sum d_c^2 - (sum d_c)^2 / M).
+__global__ __launch_bounds__(kRedThreads) void k_reduce_norms(const double* __restrict__ partials, int nblk,
+                                                              double inv_m, double smax, double* __restrict__ norms) {
+  __shared__ double sh[kRedWidth * kRedThreads];
+  const int b = blockIdx.x;
+  double acc[kRedWidth];
+  reduce_field_record(partials, nblk, b, acc, sh);
+  if (threadIdx.x == 0) {
+    const double w[6] = {1, 1, 1, 2, 2, 2};
+    double dev2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dev2 += w[c] * (acc[8 + c] - acc[2 + c] * acc[2 + c] * inv_m);
+    const double l2 = sqrt(acc[0]);
+    const double denom = smax * sqrt(fmax(dev2, 0.0));
+    norms[3 * b + 0] = l2;
+    norms[3 * b + 1] = sqrt(acc[1]);
+    norms[3 * b + 2] = denom > 0.0 ? l2 / denom : 0.0;
+  }
+}
+
+// Scratch of the allocation-free residual (eq_residual_noalloc): the partial records of up
+// to kNoAllocFields fields of at most kRedBlocks workgroups each, 7.3 MB held by every device
+// the library runs on until the process ends.  Host code never passes this name to a kernel:
+// it takes the device address from hipGetSymbolAddress (noalloc_scratch).
+static __device__ __align__(256) double scratch[(size_t)kNoAllocFields * kRedBlocks * kRedWidth];
 
 template <typename T>
 __global__ void k_check_finite(const T* __restrict__ p, size_t n, int* flag) {
@@ -897,6 +931,33 @@ hipError_t launch_div_stats(const T* div, size_t div_field, size_t div_comp, con
 hipError_t launch_reduce_final(const double* partials, int nblk, int batch, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_final, dim3(batch), dim3(kRedThreads), 0, s, partials, nblk, out);
   return hipGetLastError();
+}
+
+hipError_t launch_reduce_norms(const double* partials, int nblk, int batch, double inv_m, double smax, double* norms,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_norms, dim3(batch), dim3(kRedThreads), 0, s, partials, nblk, inv_m, smax, norms);
+  return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device, looked up once per device (each device
+// holds its own copy of the array at its own address).
+hipError_t noalloc_scratch(double** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* ptrs[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptrs[dev] = static_cast<double*>(p);
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
 }
 
 template <typename T>

@@ -88,3 +88,28 @@ def test_footprint_matches_layout():
 def test_accepted_sizes():
     for n in (4, 6, 8, 10, 12, 30, 32, 96, 160, 192, 384, 512, 640, 720, 1000, 1024):
         assert eq.footprint(n, n, n) > 0
+
+
+def test_noalloc_residual_refuses_bad_arguments_before_any_device_call():
+    """eq_residual_noalloc checks its descriptor, operator, batch limit and pointers on the
+    host; none of these paths touches a device."""
+    L = eq.lib()
+    fake = ctypes.c_void_p(0x10000)
+
+    def status(**kw):
+        base = dict(nx=16, ny=16, nz=16, batch=1, op="ddo", prec="fp64", h=1.0, flags=0)
+        base.update(kw)
+        d = eq._desc(**base)
+        return L.eq_residual_noalloc(ctypes.byref(d), None, fake, ctypes.c_void_p(0x20000000), None)
+
+    assert status(op="cdo") == 1                       # EQ_ERR_ARG: DDO only
+    assert status(batch=65) == 2                       # EQ_ERR_SIZE: beyond the static scratch
+    assert status(nx=14) == 2                          # EQ_ERR_SIZE: 7 is not a factor
+    assert status(h=-1.0) == 1
+    d = eq._desc(16, 16, 16, 1, "ddo", "fp64", 1.0, 0)
+    assert L.eq_residual_noalloc(None, None, fake, fake, None) == 1
+    assert L.eq_residual_noalloc(ctypes.byref(d), None, None, fake, None) == 1
+    assert L.eq_residual_noalloc(ctypes.byref(d), None, fake, None, None) == 1
+    # norms overlapping the field
+    assert L.eq_residual_noalloc(ctypes.byref(d), None, fake, ctypes.c_void_p(0x10008), None) == 1
+    assert "overlaps" in eq.lib().eq_last_error().decode()
