@@ -68,7 +68,14 @@ enum {
   EQ_F_CHECK_FINITE = 1u,   /* eq_project scans the input and synchronizes; NaN/Inf -> EQ_ERR_NONFINITE */
   EQ_F_CAPTURE_GRAPH = 2u,  /* eq_project records its launches once per (s_in, s_eq, s_removed) and
                                replays a hipGraph afterwards; needs a stream other than the null stream */
-  EQ_F_PERSISTENT = 4u,     /* reserved: a single persistent launch for the whole batch (rejected for now) */
+  EQ_F_PERSISTENT = 4u,     /* eq_project runs as one launch for the whole batch: workgroups take work items
+                               (forward xy planes, z columns, inverse planes) from a device-side queue in an
+                               order that lets fields overlap, each field's stages ordered by per-field counters.
+                               FP32 with nx == ny in {64, 128} and nz in {64, 128, 256} (else EQ_ERR_ARG at
+                               eq_plan).  Its z stage runs four elements per thread, as the three-pass schedule
+                               does with eq_tune zp_e = 4, whose results it equals bit for bit.  A counter wait
+                               that gives up (never expected) is reported by the next eq_residual as
+                               EQ_ERR_DEVICE. */
   EQ_F_OWN_STREAM = 8u      /* the plan creates and owns a non-blocking stream; hip_stream is ignored */
 };
 
@@ -196,13 +203,16 @@ eq_status eq_plan_reset_stats(eq_plan_t p);
  *            x kernel then holds 6 x 4 values per lane instead of 6 x 8); ignored elsewhere,
  *   xsplit   x pass kernel: 2 = six components split over the two halves of a wavefront
  *            (three rows of E values per lane; needs nx / E to divide 32), 1 = not split,
- *            0 = library default; reported as 1 or 2.
+ *            0 = library default; reported as 1 or 2,
+ *   zp_e     elements per thread of the three-pass z projection in FP32: 8 (default) or 4
+ *            (half the registers per thread, radix-4 stages); 0 = default; FP64 always uses 4;
+ *            reported as 4 or 8 on the three-pass route (4 under EQ_F_PERSISTENT), else 0.
  * Invalid shapes for this grid return EQ_ERR_ARG (EQ_ERR_SIZE if LDS would exceed the device
  * limit) and leave the plan unchanged.  Every setting computes the same transform; results
  * may differ only by floating-point rounding order when radix16 changes.
  * The EQ_TUNE environment variable ("tx_y=16,tx_z=32,rw_x=4,chunk=32,radix16=2,schedule=5") seeds the
  * tuning at eq_plan.  eq_plan_get_tune reports the settings in effect (defaults resolved). */
-typedef struct { int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4, xsplit; } eq_tune;
+typedef struct { int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4, xsplit, zp_e; } eq_tune;
 eq_status eq_plan_tune(eq_plan_t p, const eq_tune* t);
 eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t);
 

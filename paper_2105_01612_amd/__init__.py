@@ -47,7 +47,7 @@ class EqDesc(ctypes.Structure):
 class EqTune(ctypes.Structure):
     _fields_ = [("tx_y", ctypes.c_int), ("tx_z", ctypes.c_int), ("rw_x", ctypes.c_int), ("chunk", ctypes.c_int),
                 ("radix16", ctypes.c_int), ("schedule", ctypes.c_int), ("tc_zp", ctypes.c_int),
-                ("radix4", ctypes.c_int), ("xsplit", ctypes.c_int)]
+                ("radix4", ctypes.c_int), ("xsplit", ctypes.c_int), ("zp_e", ctypes.c_int)]
 
 
 class EqEmbed(ctypes.Structure):
@@ -259,18 +259,18 @@ class Plan:
         handle = _stream_handle(stream)
         _check(lib().eq_plan_set_stream(self._h, ctypes.c_void_p(handle) if handle else None), "eq_plan_set_stream")
 
-    def tune(self, tx_y=0, tx_z=0, rw_x=0, chunk=0, radix16=-1, schedule=0, tc_zp=0, radix4=0, xsplit=0):
+    def tune(self, tx_y=0, tx_z=0, rw_x=0, chunk=0, radix16=-1, schedule=0, tc_zp=0, radix4=0, xsplit=0, zp_e=0):
         """eq_plan_tune: set launch shapes / radix schedule / pass schedule (0 or -1 = default);
         raises EqError if they do not fit this grid."""
         t = EqTune(int(tx_y), int(tx_z), int(rw_x), int(chunk), int(radix16), int(schedule), int(tc_zp), int(radix4),
-                   int(xsplit))
+                   int(xsplit), int(zp_e))
         _check(lib().eq_plan_tune(self._h, ctypes.byref(t)), "eq_plan_tune")
 
     def get_tune(self):
         t = EqTune()
         _check(lib().eq_plan_get_tune(self._h, ctypes.byref(t)), "eq_plan_get_tune")
         return {"tx_y": t.tx_y, "tx_z": t.tx_z, "rw_x": t.rw_x, "chunk": t.chunk, "radix16": t.radix16,
-                "schedule": t.schedule, "tc_zp": t.tc_zp, "radix4": t.radix4, "xsplit": t.xsplit}
+                "schedule": t.schedule, "tc_zp": t.tc_zp, "radix4": t.radix4, "xsplit": t.xsplit, "zp_e": t.zp_e}
 
     def set_timing(self, enable: bool, only: str = None):
         """eq_plan_set_timing; `only` names the one pass to bracket with events (None: all)."""

@@ -111,7 +111,7 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
         if _cost(t16, Z_PASSES) < _cost(t8, Z_PASSES):
             mask |= 4
     best = {"tx_y": 0, "tx_z": 0, "rw_x": 0, "chunk": 0, "radix16": mask, "schedule": 5, "tc_zp": 0, "radix4": 0,
-            "xsplit": 0}
+            "xsplit": 0, "zp_e": 0}
     base = trial(**best)
     log = {"radix16_all8": t8, "radix16_all16": t16, "default_shapes": base}
 
@@ -158,6 +158,15 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
             log[f"tc_zp={v}"] = c
             if c < c3:
                 best3, c3 = dict(best3, tc_zp=v), c
+        # the z projection with four elements per thread (FP32): half the registers per thread
+        for v in (4, 8, 16):
+            t = trial(**dict(best3, zp_e=4, tc_zp=v))
+            if t is None or plan.get_tune()["zp_e"] != 4:
+                continue
+            c = _cost(t, ("z_proj",))
+            log[f"zp_e=4 tc_zp={v}"] = c
+            if c < c3:
+                best3, c3 = dict(best3, zp_e=4, tc_zp=v), c
         t3 = trial(**best3)
         cost3 = _cost(t3, THREE_PASSES)
         log["project_ms_five"], log["project_ms_three"] = cost5, cost3

@@ -118,7 +118,7 @@ eq_status validate(const eq_desc* d) {
   if (d->op != EQ_OP_CDO && d->op != EQ_OP_DDO) return fail(EQ_ERR_ARG, "op must be EQ_OP_CDO or EQ_OP_DDO");
   if (d->prec != EQ_FP64 && d->prec != EQ_FP32) return fail(EQ_ERR_ARG, "prec must be EQ_FP64 or EQ_FP32");
   if (!std::isfinite(d->h) || !(d->h > 0.0)) return fail(EQ_ERR_ARG, "h must be finite and > 0");
-  if (d->flags & ~(unsigned)(EQ_F_CHECK_FINITE | EQ_F_CAPTURE_GRAPH | EQ_F_OWN_STREAM))
+  if (d->flags & ~(unsigned)(EQ_F_CHECK_FINITE | EQ_F_CAPTURE_GRAPH | EQ_F_OWN_STREAM | EQ_F_PERSISTENT))
     return fail(EQ_ERR_ARG, "unknown or unsupported flag bits");
   AxisFft t;
   const int dims[3] = {d->nx, d->ny, d->nz};
@@ -135,6 +135,9 @@ eq_status validate(const eq_desc* d) {
   // total element count must be addressable by the launch grids
   const double rows = (double)d->batch * (d->nz / 2 + 1) * d->ny;
   if (rows > 2.0e9) return fail(EQ_ERR_SIZE, "batch * (nz/2+1) * ny too large for one launch");
+  if ((d->flags & EQ_F_PERSISTENT) &&
+      !persist_route_supported(Geom{d->nx, d->ny, d->nz, d->nz / 2 + 1, d->batch}, d->prec == EQ_FP64))
+    return fail(EQ_ERR_ARG, "EQ_F_PERSISTENT needs FP32 with nx == ny in {64, 128} and nz in {64, 128, 256}");
   return EQ_OK;
 }
 
@@ -165,8 +168,10 @@ double symbol_max2(const eq_desc* d) {
 
 
 struct Layout {
-  size_t w_bytes, sym_bytes, tw64_bytes, tw32_bytes, part_bytes, red_bytes, flag_bytes;
-  size_t total() const { return w_bytes + sym_bytes + tw64_bytes + tw32_bytes + part_bytes + red_bytes + flag_bytes; }
+  size_t w_bytes, sym_bytes, tw64_bytes, tw32_bytes, part_bytes, red_bytes, flag_bytes, ctr_bytes;
+  size_t total() const {
+    return w_bytes + sym_bytes + tw64_bytes + tw32_bytes + part_bytes + red_bytes + flag_bytes + ctr_bytes;
+  }
 };
 
 Layout layout_of(const eq_desc* d) {
@@ -185,16 +190,18 @@ Layout layout_of(const eq_desc* d) {
   L.part_bytes = (size_t)d->batch * kRedBlocks * kRedWidth * sizeof(double);
   L.red_bytes = 0;   // the per-field records live in pinned host memory (see eq_plan)
   L.flag_bytes = 256;
+  // persistent launch: queue head, workgroups done, error flag, spare, then two counters per field
+  L.ctr_bytes = (d->flags & EQ_F_PERSISTENT) ? (size_t)(4 + 2 * d->batch) * sizeof(unsigned) : 0;
   return L;
 }
 
 enum PassId {
   P_Z_R2C = 0, P_Y_FWD, P_X_PROJ, P_Y_INV, P_Z_C2R, P_DIV_DDO, P_X_DIV, P_Y_INV3, P_Z_C2R3, P_DIV_STATS,
-  P_REDUCE, P_CHECK, P_X_FWD, P_PROJ_ONLY, P_PLANE_R2C, P_Z_PROJ, P_PLANE_C2R, P_X_POT, P_COUNT
+  P_REDUCE, P_CHECK, P_X_FWD, P_PROJ_ONLY, P_PLANE_R2C, P_Z_PROJ, P_PLANE_C2R, P_X_POT, P_PERSIST, P_COUNT
 };
 const char* kPassNames[P_COUNT] = {
   "z_r2c", "y_fwd", "x_proj", "y_inv", "z_c2r", "div_ddo", "x_div", "y_inv3", "z_c2r3", "div_stats",
-  "reduce_final", "check_finite", "x_fwd", "proj_only", "plane_r2c", "z_proj", "plane_c2r", "x_pot"};
+  "reduce_final", "check_finite", "x_fwd", "proj_only", "plane_r2c", "z_proj", "plane_c2r", "x_pot", "persist"};
 
 struct TimingRec { int pass; hipEvent_t a, b; };
 
@@ -217,6 +224,7 @@ struct eq_plan_s {
   double* red_dev = nullptr;    // ... which the final reduction kernel writes through this alias
   double smax2 = 0.0;           // max_q |s(q)|^2 of the operator's symbol (for the relative residual)
   int* flag = nullptr;
+  unsigned* ctr = nullptr;      // persistent launch counters (EQ_F_PERSISTENT)
   // timing
   bool timing = false;
   int timing_pass = -1;      // -1: every pass, else the one pass id bracketed by events
@@ -237,8 +245,15 @@ namespace {
 // (projection).
 const double* sym_unit(const eq_plan_s* p) { return p->sym + (p->g.nx + p->g.ny + p->g.nz); }
 
+// The three-pass z projection with four elements per thread (FP32): asked for, or the persistent
+// launch's z stage.
+bool zp_e4(const eq_plan_s* p, const Tune& tn) {
+  return p->desc.prec == EQ_FP32 && (tn.zp_e == 4 || (p->desc.flags & EQ_F_PERSISTENT));
+}
+
 // Whether eq_project takes the three-pass route under tuning tn.
 bool use_plane(const eq_plan_s* p, const Tune& tn) {
+  if (p->desc.flags & EQ_F_PERSISTENT) return true;          // one persistent launch of the three passes
   if (tn.schedule == 5 || !plane_route_supported(p->g, p->desc.prec == EQ_FP64)) return false;
   // default: three passes where a plane leaves the workgroup room to breathe (nx <= 128);
   // a 256^2 FP32 plane fills a CU's registers and runs no faster than five passes
@@ -261,6 +276,9 @@ double pass_bytes(const eq_plan_s* p, int pass) {
     case P_PLANE_R2C: return B * 6 * (M * es + Q3);
     case P_Z_PROJ: return B * 6 * 2 * Q3;
     case P_PLANE_C2R: return B * 6 * (Q3 + M * es) + (p->last_removed ? B * 6 * 2 * M * es : 0.0);
+    case P_PERSIST:     // the three passes
+      return B * 6 * (M * es + Q3) + B * 6 * 2 * Q3 + B * 6 * (Q3 + M * es) +
+             (p->last_removed ? B * 6 * 2 * M * es : 0.0);
     case P_DIV_DDO: return B * 6 * M * es;
     case P_X_DIV: case P_X_POT: return B * (6 * Q + 3 * Q);
     case P_Y_INV3: return B * 3 * 2 * Q;
@@ -331,6 +349,7 @@ void release(eq_plan_s* p) {
   if (p->partials) (void)hipFree(p->partials);
   if (p->red) (void)hipHostFree(p->red);
   if (p->flag) (void)hipFree(p->flag);
+  if (p->ctr) (void)hipFree(p->ctr);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
@@ -369,7 +388,7 @@ eq_status check_shapes(const eq_plan_s* p, const Tune& tn) {
                             "{64, 128, 256}");
   size_t need = std::max(lds_y(g, p->ay, eb, tn), std::max(lds_z(g, p->az, eb, tn), lds_x(g, p->ax, eb, tn)));
   if (use_plane(p, tn)) {
-    const int tc = pick_tc_zproj(g, fp64, tn.tc_zp);
+    const int tc = pick_tc_zproj(g, fp64, tn.tc_zp, zp_e4(p, tn));
     if (tn.tc_zp < 0 || (tn.tc_zp > 0 && tc != tn.tc_zp)) return fail(EQ_ERR_ARG, "tc_zp does not fit this grid");
     need = std::max(need, std::max(plane_lds(g, fp64), zproj_lds(g, fp64, tc)));
   }
@@ -403,6 +422,7 @@ Tune tune_from_env() {
       else if (key == "xsplit") t.xsplit = val;
       else if (key == "schedule") t.schedule = val;
       else if (key == "tc_zp") t.tc_zp = val;
+      else if (key == "zp_e") t.zp_e = val;
     }
     pos = end + 1;
   }
@@ -441,10 +461,11 @@ eq_status run_project_plane(eq_plan_s* p, const void* s_in, void* s_eq, void* s_
   const C* twz = tw + p->g.nx + p->g.ny;
   const Geom& g = p->g;
   hipStream_t s = p->stream;
-  const int tc = pick_tc_zproj(g, p->desc.prec == EQ_FP64, p->tune.tc_zp);
+  const int tc = pick_tc_zproj(g, p->desc.prec == EQ_FP64, p->tune.tc_zp, zp_e4(p, p->tune));
   EQ_HIP(timed(p, P_PLANE_R2C, [&] { return launch_plane_r2c<T>(static_cast<const T*>(s_in), W, g, twx, twy, s); }),
          "plane_r2c launch");
-  EQ_HIP(timed(p, P_Z_PROJ, [&] { return launch_zproj<T>(W, g, twz, sym_unit(p), tc, s); }), "z_proj launch");
+  EQ_HIP(timed(p, P_Z_PROJ, [&] { return launch_zproj<T>(W, g, twz, sym_unit(p), tc, zp_e4(p, p->tune), s); }),
+         "z_proj launch");
   EQ_HIP(timed(p, P_PLANE_C2R, [&] {
            return launch_plane_c2r<T>(W, static_cast<T*>(s_eq), static_cast<const T*>(s_in), static_cast<T*>(s_removed),
                                       g, twx, twy, s);
@@ -453,11 +474,29 @@ eq_status run_project_plane(eq_plan_s* p, const void* s_in, void* s_eq, void* s_
   return EQ_OK;
 }
 
+// EQ_F_PERSISTENT: the three passes as one launch over a device-side work queue.
+template <typename T>
+eq_status run_project_persist(eq_plan_s* p, const void* s_in, void* s_eq, void* s_removed) {
+  using C = cplx<T>;
+  C* W = static_cast<C*>(p->W);
+  const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
+  const Geom& g = p->g;
+  EQ_HIP(timed(p, P_PERSIST, [&] {
+           return launch_persist<T>(static_cast<const T*>(s_in), W, static_cast<T*>(s_eq), static_cast<T*>(s_removed), g,
+                                    tw, tw + g.nx, tw + g.nx + g.ny, sym_unit(p), p->ctr, p->stream);
+         }),
+         "persistent launch");
+  return EQ_OK;
+}
+
 // e.on: the real fields are a sample embedded in the box (five passes; the z passes read
 // the sample with a zero buffer around it and write the sample's voxels only).
 template <typename T>
 eq_status run_project(eq_plan_s* p, const void* s_in, void* s_eq, void* s_removed, const Embed& e = Embed{}) {
   using C = cplx<T>;
+  if constexpr (sizeof(T) == 4) {
+    if (!e.on && (p->desc.flags & EQ_F_PERSISTENT)) return run_project_persist<T>(p, s_in, s_eq, s_removed);
+  }
   if (!e.on && use_plane(p, p->tune)) return run_project_plane<T>(p, s_in, s_eq, s_removed);
   C* W = static_cast<C*>(p->W);
   const C* tw = reinterpret_cast<const C*>(sizeof(T) == 8 ? (const void*)p->tw64 : (const void*)p->tw32);
@@ -588,6 +627,12 @@ eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out
   EQ_HIP(timed(p, P_REDUCE, [&] { return launch_reduce_final(p->partials, nred, g.batch, p->red_dev, st); }),
          "reduce launch");
   EQ_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (p->ctr) {
+    // a persistent launch whose dependency wait gave up (never expected) is reported here
+    unsigned gave_up = 0;
+    EQ_HIP(hipMemcpy(&gave_up, p->ctr + 2, sizeof(unsigned), hipMemcpyDeviceToHost), "hipMemcpy(counters)");
+    if (gave_up) return fail(EQ_ERR_DEVICE, "a persistent projection's dependency wait gave up; its output is invalid");
+  }
   const double* host = p->red;
   const double smax2 = p->smax2;
   const double w[6] = {1, 1, 1, 2, 2, 2};
@@ -680,9 +725,14 @@ eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out) {
       (st = dev_alloc((void**)&p->tw64, L.tw64_bytes, "twiddles64")) != EQ_OK ||
       (st = dev_alloc((void**)&p->tw32, L.tw32_bytes, "twiddles32")) != EQ_OK ||
       (st = dev_alloc((void**)&p->partials, L.part_bytes, "partials")) != EQ_OK ||
-      (st = dev_alloc((void**)&p->flag, L.flag_bytes, "flag")) != EQ_OK) {
+      (st = dev_alloc((void**)&p->flag, L.flag_bytes, "flag")) != EQ_OK ||
+      (L.ctr_bytes && (st = dev_alloc((void**)&p->ctr, L.ctr_bytes, "persistent counters")) != EQ_OK)) {
     release(p);
     return st;
+  }
+  if (p->ctr) {
+    e = launch_fill_int(reinterpret_cast<int*>(p->ctr), (int)(L.ctr_bytes / sizeof(unsigned)), 0, p->stream);
+    if (e != hipSuccess) { release(p); return hip_fail(e, "counter fill launch"); }
   }
   // the residual's per-field records go straight to pinned, device-mapped host memory:
   // no copy engine and no pageable staging between the last kernel and the host
@@ -856,6 +906,7 @@ eq_status eq_plan_tune(eq_plan_t p, const eq_tune* tv) {
   if (tv->radix16 < -1 || tv->radix16 > 7) return fail(EQ_ERR_ARG, "radix16 must be -1 or a mask of 1|2|4");
   if (tv->radix4 != 0 && tv->radix4 != 1) return fail(EQ_ERR_ARG, "radix4 must be 0 or 1 (x axis)");
   if (tv->xsplit < 0 || tv->xsplit > 2) return fail(EQ_ERR_ARG, "xsplit must be 0, 1 or 2");
+  if (tv->zp_e != 0 && tv->zp_e != 4 && tv->zp_e != 8) return fail(EQ_ERR_ARG, "zp_e must be 0, 4 or 8");
   Tune t;
   t.tx_y = tv->tx_y; t.tx_z = tv->tx_z; t.rw_x = tv->rw_x; t.chunk = tv->chunk;
   t.radix16 = tv->radix16;
@@ -863,6 +914,7 @@ eq_status eq_plan_tune(eq_plan_t p, const eq_tune* tv) {
   t.xsplit = tv->xsplit;
   t.schedule = tv->schedule;
   t.tc_zp = tv->tc_zp;
+  t.zp_e = tv->zp_e;
   DeviceGuard dg(p->device);
   const AxisFft ax = p->ax, ay = p->ay, az = p->az;
   set_axes(p, t.radix16, t.radix4);
@@ -889,7 +941,8 @@ eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t) {
   t->xsplit = x_split(p->ax, eb, p->tune) ? 2 : 1;
   const bool plane = use_plane(p, p->tune);
   t->schedule = plane ? 3 : 5;
-  t->tc_zp = plane ? pick_tc_zproj(p->g, p->desc.prec == EQ_FP64, p->tune.tc_zp) : 0;
+  t->tc_zp = plane ? pick_tc_zproj(p->g, p->desc.prec == EQ_FP64, p->tune.tc_zp, zp_e4(p, p->tune)) : 0;
+  t->zp_e = plane ? (zp_e4(p, p->tune) || p->desc.prec == EQ_FP64 ? 4 : 8) : 0;
   return EQ_OK;
 }
 

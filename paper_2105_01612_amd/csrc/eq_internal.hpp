@@ -34,6 +34,7 @@ struct Tune {
   int tc_zp = 0;     // columns per workgroup of the three-pass z projection
   int radix4 = 0;    // 1: radix-4 stages on x (six-component x kernel, FP32 powers of two)
   int xsplit = 0;    // six-component x kernel split over wavefront halves: 1 = off, 2 = on, 0 = default
+  int zp_e = 0;      // elements per thread of the three-pass z projection in FP32: 8 or 4 (0 = default 8)
 };
 
 // Lateral embedding of a sample in the periodic box (the zero-stress buffer of Sections 3.3
@@ -118,18 +119,28 @@ hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s);
 // complex; a plane is (field, component, z).
 bool plane_route_supported(const Geom& g, bool fp64);
 size_t plane_lds(const Geom& g, bool fp64);
-int pick_tc_zproj(const Geom& g, bool fp64, int want);
+int pick_tc_zproj(const Geom& g, bool fp64, int want, bool e4);
 size_t zproj_lds(const Geom& g, bool fp64, int tc);
 
 template <typename T>
 hipError_t launch_plane_r2c(const T* in, cplx<T>* W2, const Geom& g, const cplx<T>* twx, const cplx<T>* twy,
                             hipStream_t s);
 template <typename T>
-hipError_t launch_zproj(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, hipStream_t s);
+// e4: four elements per thread along z (FP32; FP64 always takes four)
+hipError_t launch_zproj(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, bool e4,
+                        hipStream_t s);
 // out, removed (nullable): field layout; removed = in - out
 template <typename T>
 hipError_t launch_plane_c2r(const cplx<T>* W2, T* out, const T* in, T* removed, const Geom& g, const cplx<T>* twx,
                             const cplx<T>* twy, hipStream_t s);
+
+// Persistent three-pass launch (EQ_F_PERSISTENT, FP32): nx == ny in {64, 128}, nz in {64, 128,
+// 256}.  ctr: 4 + 2 * batch counters, zero before the first launch (each launch leaves them zero,
+// except ctr[2], raised if a dependency wait gave up).
+bool persist_route_supported(const Geom& g, bool fp64);
+template <typename T>
+hipError_t launch_persist(const T* in, cplx<T>* W2, T* out, T* removed, const Geom& g, const cplx<T>* twx,
+                          const cplx<T>* twy, const cplx<T>* twz, const double* symu, unsigned* ctr, hipStream_t s);
 
 // Launch shapes (exposed so the plan can check LDS against the device limit).
 int pick_tx_y(const Geom& g, const AxisFft& ay, int elem_bytes, const Tune& tn);

@@ -23,6 +23,8 @@
 // the same way.  The inverse path undoes both packings.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "eq_fft.hpp"
 #include "eq_internal.hpp"
 #include "eq_kernels_impl.hpp"
@@ -56,24 +58,23 @@ struct PlaneShape {
   static_assert(PY % 2 == 0, "rows 2j and 2j+1 of one y-column belong to neighbouring threads");
 };
 
+// Forward plane `plane` of `planes` (one workgroup; LDS of PlaneShape::lds_elems at `lds`).
 template <typename T, int NX, int NY, int NT, typename FX, typename FY>
-__global__ __launch_bounds__(NT) void k_plane_r2c(const T* __restrict__ in, cplx<T>* __restrict__ W2,
-                                                  const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy) {
+__device__ __forceinline__ void plane_r2c_body(const T* __restrict__ in, cplx<T>* __restrict__ W2, int plane,
+                                               int planes, const cplx<T>* __restrict__ twx,
+                                               const cplx<T>* __restrict__ twy, cplx<T>* lds, int tid) {
   using C = cplx<T>;
   using S = PlaneShape<T, NX, NY, NT, FX, FY>;
   constexpr int EX = S::EX, PX = S::PX, LX = S::LX, RX = S::RX;
   constexpr int EY = S::EY, PY = S::PY, LY = S::LY, RY = S::RY, NXH = S::NXH, TS = S::TS;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
   C* ZA = lds;
   C* ZB = lds + S::NJ * TS;
   C* YX = lds + S::YOFF;
   C* CB = lds + S::COFF;
   const FftDesc dd{};
-  const T* src = in + (size_t)blockIdx.x * (NX * NY);
-  C* dst = W2 + (size_t)blockIdx.x * (NXH * NY);
-  C* dstn = W2 + (size_t)gridDim.x * (NXH * NY) + (size_t)blockIdx.x * NY;   // Nyquist column
-  const int tid = threadIdx.x;
+  const T* src = in + (size_t)plane * (NX * NY);
+  C* dst = W2 + (size_t)plane * (NXH * NY);
+  C* dstn = W2 + (size_t)planes * (NXH * NY) + (size_t)plane * NY;   // Nyquist column
   const int px = tid % PX, lx = tid / PX;
   // ---- x phase: packed line j = lx + r*LX holds rows 2j (real part) and 2j+1 (imaginary part)
   C v[RX][EX];
@@ -147,23 +148,29 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* __restrict__ in, cplx
 }
 
 template <typename T, int NX, int NY, int NT, typename FX, typename FY>
-__global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2, T* __restrict__ out,
-                                                  const T* __restrict__ in, T* __restrict__ removed,
-                                                  const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
-                                                  T scale) {
+__global__ __launch_bounds__(NT) void k_plane_r2c(const T* __restrict__ in, cplx<T>* __restrict__ W2,
+                                                  const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy) {
+  extern __shared__ unsigned char smem_raw[];
+  plane_r2c_body<T, NX, NY, NT, FX, FY>(in, W2, blockIdx.x, gridDim.x, twx, twy, reinterpret_cast<cplx<T>*>(smem_raw),
+                                        threadIdx.x);
+}
+
+// Inverse plane `plane` of `planes`.
+template <typename T, int NX, int NY, int NT, typename FX, typename FY>
+__device__ __forceinline__ void plane_c2r_body(const cplx<T>* __restrict__ W2, T* __restrict__ out,
+                                               const T* __restrict__ in, T* __restrict__ removed, int plane,
+                                               int planes, const cplx<T>* __restrict__ twx,
+                                               const cplx<T>* __restrict__ twy, T scale, cplx<T>* lds, int tid) {
   using C = cplx<T>;
   using S = PlaneShape<T, NX, NY, NT, FX, FY>;
   constexpr int EX = S::EX, PX = S::PX, LX = S::LX, RX = S::RX;
   constexpr int EY = S::EY, PY = S::PY, LY = S::LY, RY = S::RY, NXH = S::NXH, TS = S::TS;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
   C* TT = lds;                     // NY rows x LY columns of the round's real-row spectra
   C* YX = lds + S::YOFF;
   const FftDesc dd{};
-  const C* src = W2 + (size_t)blockIdx.x * (NXH * NY);
-  const C* srcn = W2 + (size_t)gridDim.x * (NXH * NY) + (size_t)blockIdx.x * NY;   // Nyquist column
-  const size_t obase = (size_t)blockIdx.x * (NX * NY);
-  const int tid = threadIdx.x;
+  const C* src = W2 + (size_t)plane * (NXH * NY);
+  const C* srcn = W2 + (size_t)planes * (NXH * NY) + (size_t)plane * NY;   // Nyquist column
+  const size_t obase = (size_t)plane * (NX * NY);
   const int px = tid % PX, lx = tid / PX;
   const int cy = tid % LY, py = tid / LY;
   const LdsMap my{1, LY, 0};
@@ -245,6 +252,16 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2
   }
 }
 
+template <typename T, int NX, int NY, int NT, typename FX, typename FY>
+__global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2, T* __restrict__ out,
+                                                  const T* __restrict__ in, T* __restrict__ removed,
+                                                  const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
+                                                  T scale) {
+  extern __shared__ unsigned char smem_raw[];
+  plane_c2r_body<T, NX, NY, NT, FX, FY>(W2, out, in, removed, blockIdx.x, gridDim.x, twx, twy, scale,
+                                        reinterpret_cast<cplx<T>*>(smem_raw), threadIdx.x);
+}
+
 // ------------------------------------------------------------ z pass -------
 
 // Raw buffer access (resource word 3 in eq_kernels_impl.hpp); the range in the resource
@@ -283,25 +300,21 @@ struct ZpArgs {
 // Thread (col, p) owns elements kz = p + i*P of the six component columns of one
 // (ky, kx); the forward DFTs, the projection and the inverse DFTs run in registers,
 // with the LDS exchanges of consecutive transforms alternating between two regions.
+// Z tiles of a field: ny * nx/2 / tc over W2 (kx < nx/2), then ny / tc over the Nyquist columns.
+__host__ __device__ __forceinline__ int zproj_tiles(const ZpArgs& a) { return a.ny * (a.nx / 2) / a.tc + a.ny / a.tc; }
+
+// Tile `tile` of field `b` (one workgroup of tc * NZ / E threads).
 template <typename T, typename FZ>
-__global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__ W2, ZpArgs a,
-                                                           const cplx<T>* __restrict__ tw,
-                                                           const double* __restrict__ sym) {
+__device__ __forceinline__ void zproj_body(cplx<T>* __restrict__ W2, const ZpArgs& a, const cplx<T>* __restrict__ tw,
+                                           const double* __restrict__ sym, int tile, int b, cplx<T>* lds, int tid) {
   using C = cplx<T>;
   constexpr int E = FZ::E, NZ = FZ::N, P = NZ / E;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
   const FftDesc dd{};
   // columns: ny * nx/2 of W2 (kx < nx/2), then ny Nyquist columns of W2N; a tile lies
   // wholly in one of the two, so its base and column stride are workgroup-uniform
   const int half = a.nx / 2;
-  const int ntm = a.ny * half / a.tc, ntile = ntm + a.ny / a.tc;
-  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range of
-  // tiles so that neighbouring narrow tiles share the 128-byte lines of their L2
-  int bid = blockIdx.x;
-  if ((gridDim.x & 7) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
-  const int tile = bid % ntile, b = bid / ntile;
-  const int col = threadIdx.x % a.tc, p = threadIdx.x / a.tc;
+  const int ntm = a.ny * half / a.tc;
+  const int col = tid % a.tc, p = tid / a.tc;
   const bool nyq = tile >= ntm;
   const int plane = nyq ? a.ny : a.ny * half;
   const int f = (nyq ? tile - ntm : tile) * a.tc + col;
@@ -343,6 +356,155 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__
     for (int i = 0; i < E; ++i) buf_store<T>(rs, voff, soff(c, i), v[c][i]);
 }
 
+template <typename T, typename FZ>
+__global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__ W2, ZpArgs a,
+                                                           const cplx<T>* __restrict__ tw,
+                                                           const double* __restrict__ sym) {
+  extern __shared__ unsigned char smem_raw[];
+  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range of
+  // tiles so that neighbouring narrow tiles share the 128-byte lines of their L2
+  int bid = blockIdx.x;
+  if ((gridDim.x & 7) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  const int ntile = zproj_tiles(a);
+  zproj_body<T, FZ>(W2, a, tw, sym, bid % ntile, bid / ntile, reinterpret_cast<cplx<T>*>(smem_raw), threadIdx.x);
+}
+
+// ---------------------------------------------------------- persistent -----
+
+// One launch runs the three passes of a whole batch.  Workgroups claim work items in queue
+// order from a device-side counter.  Queue step s holds the forward planes of field s, the z
+// tiles of field s - 1 and the inverse planes of field s - 2, so an item only ever waits for
+// items earlier in the queue (claimed by workgroups that are running), and stages of
+// different fields overlap.  A z item of field b starts once every forward item of b is done,
+// an inverse item once every z item of b is done: per-field counters, raised after an item's
+// stores are complete and written back (agent-scope release), read before the item's loads
+// (agent-scope acquire).  Each item runs the same code as its pass kernel, so results are
+// bitwise those of the three launches; no output is written by an atomic.
+struct PsArgs {
+  int batch, nz;
+  int gp, gt;               // planes per plane item, tiles per z item
+  int nP, nZ;               // items per field of each plane stage, of the z stage
+  unsigned* ctr;            // [0] queue head, [1] workgroups done, [2] a bounded wait gave up,
+                            // [4 + b] forward items done of field b, [4 + batch + b] z items done
+  unsigned spin_limit;      // polls of a dependency before giving up (the kernel always ends)
+};
+
+// Item q of the queue -> (stage 0 forward planes | 1 z tiles | 2 inverse planes, field, index).
+__device__ __forceinline__ void ps_decode(const PsArgs& a, int q, int& stage, int& b, int& j) {
+  for (int s = 0;; ++s) {
+    if (s < a.batch) {
+      if (q < a.nP) { stage = 0; b = s; j = q; return; }
+      q -= a.nP;
+    }
+    if (s >= 1 && s <= a.batch) {
+      if (q < a.nZ) { stage = 1; b = s - 1; j = q; return; }
+      q -= a.nZ;
+    }
+    if (s >= 2 && s <= a.batch + 1) {
+      if (q < a.nP) { stage = 2; b = s - 2; j = q; return; }
+      q -= a.nP;
+    }
+  }
+}
+
+template <typename T, int N, int NT, typename FX, typename FY, typename FZ>
+__global__ __launch_bounds__(NT) void k_persist(const T* __restrict__ in, cplx<T>* __restrict__ W2, T* __restrict__ out,
+                                               T* __restrict__ removed, PsArgs a, ZpArgs za,
+                                               const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
+                                               const cplx<T>* __restrict__ twz, const double* __restrict__ symu,
+                                               T scale) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  __shared__ int s_item;
+  const int fplanes = 6 * a.nz;                       // planes of one field
+  const int planes = a.batch * fplanes;
+  const int ntile = zproj_tiles(za);
+  const int total = a.batch * (2 * a.nP + a.nZ);
+  unsigned* ctr = a.ctr;
+  // Wave 0 keeps the queue and the counters, with branches on a wave-uniform value only: a
+  // branch on the thread index next to a barrier lets the compiler merge the publish of one
+  // item with the claim of the next into one thread-0 region that the other lanes skip, and
+  // then the other waves pass the barrier at the top of the loop before the claim.  Each
+  // counter operation runs on the whole wave and adds lane 0's one (the others add zero).
+  const bool w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) < 64;
+  const unsigned one = (threadIdx.x & 63) == 0 ? 1u : 0u;
+  for (;;) {
+    if (w0) s_item = __builtin_amdgcn_readfirstlane((int)atomicAdd(&ctr[0], one));
+    __syncthreads();
+    // the item is read into a scalar register, so the loop exit and the stage branches are
+    // uniform for the compiler too
+    const int q = __builtin_amdgcn_readfirstlane(s_item);
+    if (q >= total) break;
+    int stage = 0, b = 0, j = 0;
+    ps_decode(a, q, stage, b, j);
+    // the thread index passes through an empty asm per item, so that no body's index
+    // arithmetic is hoisted out of the item loop (it would stay live across the others)
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if (stage > 0) {
+      if (w0) {
+        unsigned* cnt = &ctr[4 + (stage == 1 ? 0 : a.batch) + b];
+        const unsigned need = stage == 1 ? (unsigned)a.nP : (unsigned)a.nZ;
+        unsigned polls = 0;
+        while ((unsigned)__builtin_amdgcn_readfirstlane(
+                   (int)__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
+          // give up past the limit, or at once when another wait already has
+          if (++polls > a.spin_limit ||
+              ((polls & 255u) == 0 &&
+               __builtin_amdgcn_readfirstlane(
+                   (int)__hip_atomic_load(&ctr[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)) {
+            atomicOr(&ctr[2], one);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __syncthreads();
+    }
+    if (stage == 1) {
+      for (int k = 0; k < a.gt; ++k) {
+        const int tile = j * a.gt + k;
+        if (tile < ntile) zproj_body<T, FZ>(W2, za, twz, symu, tile, b, lds, tid);
+        __syncthreads();
+      }
+    } else {
+      for (int k = 0; k < a.gp; ++k) {
+        const int pf = j * a.gp + k;
+        if (pf < fplanes) {
+          const int plane = b * fplanes + pf;
+          if (stage == 0) plane_r2c_body<T, N, N, NT, FX, FY>(in, W2, plane, planes, twx, twy, lds, tid);
+          else plane_c2r_body<T, N, N, NT, FX, FY>(W2, out, in, removed, plane, planes, twx, twy, scale, lds, tid);
+        }
+        __syncthreads();
+      }
+    }
+    if (stage < 2) {
+      // every wave's stores complete before the item is published
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (w0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        atomicAdd(&ctr[4 + (stage == 0 ? 0 : a.batch) + b], one);
+      }
+    }
+  }
+  // the last workgroup to finish resets the counters for the next launch: every other one has
+  // made its final claim, so nothing reads them any more
+  if (w0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned done = (unsigned)__builtin_amdgcn_readfirstlane((int)atomicAdd(&ctr[1], one));
+    if (done == gridDim.x - 1) {
+      for (int i = (int)(threadIdx.x & 63); i < 2 * a.batch; i += 64)
+        __hip_atomic_store(&ctr[4 + i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (one) {
+        __hip_atomic_store(&ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ dispatch -----
 
 // radix-8 stages throughout (radix 16 needs more registers than a resident plane leaves)
@@ -365,6 +527,11 @@ template <> struct ZCfg<float, 256> { using F = Sched<8, 8, 4>; };
 template <> struct ZCfg<double, 64> { using F = Sched<4, 4, 4>; };
 template <> struct ZCfg<double, 128> { using F = Sched<4, 4, 4, 2>; };
 template <> struct ZCfg<double, 256> { using F = Sched<4, 4, 4, 4>; };
+// four elements per thread in FP32: half the registers (the persistent launch's z stage)
+template <typename T, int NZ> struct ZCfg4;
+template <> struct ZCfg4<float, 64> { using F = Sched<4, 4, 4>; };
+template <> struct ZCfg4<float, 128> { using F = Sched<4, 4, 4, 2>; };
+template <> struct ZCfg4<float, 256> { using F = Sched<4, 4, 4, 4>; };
 
 template <typename T, int N>
 size_t plane_lds_bytes() {
@@ -407,9 +574,8 @@ hipError_t plane_c2r_n(const cplx<T>* W2, T* out, const T* in, T* removed, const
   return hipGetLastError();
 }
 
-template <typename T, int NZ>
+template <typename T, int NZ, typename F = typename ZCfg<T, NZ>::F>
 hipError_t zproj_n(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, hipStream_t s) {
-  using F = typename ZCfg<T, NZ>::F;
   const ZpArgs a{g.nx, g.ny, g.nz, tc, g.batch};
   if ((double)6 * NZ * g.ny * (g.nx / 2) * sizeof(cplx<T>) >= 4294967296.0) return hipErrorInvalidValue;  // 32-bit offsets
   if (tc < 1 || g.ny % tc != 0 || tc * (NZ / F::E) > kMaxFastThreads) return hipErrorInvalidValue;
@@ -423,7 +589,78 @@ hipError_t zproj_n(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double*
 
 bool plane_edge_ok(int n) { return n == 64 || n == 128 || n == 256; }
 
+// Persistent launch: one workgroup shape for all three stages (the plane kernel's), so the z
+// tiles are NT / (NZ / E) columns wide.
+// Plane shape of the persistent launch: 512 threads at 128 (half the plane registers per thread
+// of the 256-thread pass kernel; the transforms, and so the results, are the same).
+template <typename T, int N> struct PersistPlaneCfg : PlaneCfg<T, N> {};
+template <> struct PersistPlaneCfg<float, 128> { static constexpr int NT = 512; using FX = Sched<8, 8, 2>; using FY = FX; };
+
+template <typename T, int N, int NZ>
+hipError_t persist_n(const T* in, cplx<T>* W2, T* out, T* removed, const Geom& g, const cplx<T>* twx,
+                     const cplx<T>* twy, const cplx<T>* twz, const double* symu, unsigned* ctr, hipStream_t s) {
+  using Cf = PersistPlaneCfg<T, N>;
+  using FX = typename Cf::FX;
+  using FY = typename Cf::FY;
+  using FZ = typename ZCfg4<T, NZ>::F;
+  constexpr int NT = Cf::NT, PZ = NZ / FZ::E, TC = NT / PZ;
+  static_assert(TC >= 1 && N % TC == 0, "z tiles must divide the Nyquist column count");
+  if ((double)6 * NZ * g.ny * (g.nx / 2) * sizeof(cplx<T>) >= 4294967296.0) return hipErrorInvalidValue;  // 32-bit offsets
+  const ZpArgs za{g.nx, g.ny, g.nz, TC, g.batch};
+  PsArgs a{};
+  a.batch = g.batch;
+  a.nz = g.nz;
+  a.gp = N * N >= 16384 ? 1 : 16384 / (N * N);          // about 64 K elements per plane item
+  a.gt = 1;
+  a.nP = (6 * g.nz + a.gp - 1) / a.gp;
+  a.nZ = (zproj_tiles(za) + a.gt - 1) / a.gt;
+  a.ctr = ctr;
+  a.spin_limit = 1u << 18;
+  const size_t lds =
+      std::max(PlaneShape<T, N, N, NT, FX, FY>::lds_elems * sizeof(cplx<T>), zproj_lds(g, sizeof(T) == 8, TC));
+  const void* k = reinterpret_cast<const void*>(&k_persist<T, N, NT, FX, FY, FZ>);
+  static const hipError_t once = allow_lds(k, lds);
+  if (once != hipSuccess) return once;
+  // as many workgroups as the device holds at once, at most one per item
+  static const int cap = [&] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, NT, lds) != hipSuccess)
+      return 256;
+    return std::max(1, cus * per);
+  }();
+  const int total = g.batch * (2 * a.nP + a.nZ);
+  const int grid = std::max(1, std::min(cap, total));
+  const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
+  hipLaunchKernelGGL((k_persist<T, N, NT, FX, FY, FZ>), dim3(grid), dim3(NT), lds, s, in, W2, out, removed, a, za, twx,
+                     twy, twz, symu, scale);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+bool persist_route_supported(const Geom& g, bool fp64) {
+  return !fp64 && g.nx == g.ny && (g.nx == 64 || g.nx == 128) && plane_edge_ok(g.nz);
+}
+
+template <typename T>
+hipError_t launch_persist(const T* in, cplx<T>* W2, T* out, T* removed, const Geom& g, const cplx<T>* twx,
+                          const cplx<T>* twy, const cplx<T>* twz, const double* symu, unsigned* ctr, hipStream_t s) {
+  static_assert(sizeof(T) == 4, "the persistent launch is FP32");
+  if (!persist_route_supported(g, false)) return hipErrorInvalidValue;
+  if (g.nx == 64) {
+    switch (g.nz) {
+      case 64: return persist_n<T, 64, 64>(in, W2, out, removed, g, twx, twy, twz, symu, ctr, s);
+      case 128: return persist_n<T, 64, 128>(in, W2, out, removed, g, twx, twy, twz, symu, ctr, s);
+      default: return persist_n<T, 64, 256>(in, W2, out, removed, g, twx, twy, twz, symu, ctr, s);
+    }
+  }
+  switch (g.nz) {
+    case 64: return persist_n<T, 128, 64>(in, W2, out, removed, g, twx, twy, twz, symu, ctr, s);
+    case 128: return persist_n<T, 128, 128>(in, W2, out, removed, g, twx, twy, twz, symu, ctr, s);
+    default: return persist_n<T, 128, 256>(in, W2, out, removed, g, twx, twy, twz, symu, ctr, s);
+  }
+}
 
 bool plane_route_supported(const Geom& g, bool fp64) {
   if (g.nx != g.ny || !plane_edge_ok(g.nx) || !plane_edge_ok(g.nz)) return false;
@@ -438,9 +675,9 @@ size_t plane_lds(const Geom& g, bool fp64) {
   }
 }
 
-int pick_tc_zproj(const Geom& g, bool fp64, int want) {
+int pick_tc_zproj(const Geom& g, bool fp64, int want, bool e4) {
   const int plane = g.ny;      // tiles must divide the Nyquist columns too (and so every row of W2)
-  const int P = g.nz / (fp64 ? 4 : 8);
+  const int P = g.nz / (fp64 || e4 ? 4 : 8);
   int tc = want > 0 ? want : (fp64 ? 8 : 16);     // 128-byte row segments per component
   if (tc < 1) tc = 1;
   while (tc > 1 && (plane % tc != 0 || tc * P > kMaxFastThreads)) tc >>= 1;
@@ -478,7 +715,18 @@ hipError_t launch_plane_c2r(const cplx<T>* W2, T* out, const T* in, T* removed, 
 }
 
 template <typename T>
-hipError_t launch_zproj(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, hipStream_t s) {
+hipError_t launch_zproj(cplx<T>* W2, const Geom& g, const cplx<T>* twz, const double* symu, int tc, bool e4,
+                        hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (e4) {
+      switch (g.nz) {
+        case 64: return zproj_n<T, 64, typename ZCfg4<T, 64>::F>(W2, g, twz, symu, tc, s);
+        case 128: return zproj_n<T, 128, typename ZCfg4<T, 128>::F>(W2, g, twz, symu, tc, s);
+        case 256: return zproj_n<T, 256, typename ZCfg4<T, 256>::F>(W2, g, twz, symu, tc, s);
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
   switch (g.nz) {
     case 64: return zproj_n<T, 64>(W2, g, twz, symu, tc, s);
     case 128: return zproj_n<T, 128>(W2, g, twz, symu, tc, s);
@@ -495,9 +743,12 @@ template hipError_t launch_plane_c2r<float>(const cplx<float>*, float*, const fl
                                             const cplx<float>*, const cplx<float>*, hipStream_t);
 template hipError_t launch_plane_c2r<double>(const cplx<double>*, double*, const double*, double*, const Geom&,
                                              const cplx<double>*, const cplx<double>*, hipStream_t);
-template hipError_t launch_zproj<float>(cplx<float>*, const Geom&, const cplx<float>*, const double*, int,
+template hipError_t launch_zproj<float>(cplx<float>*, const Geom&, const cplx<float>*, const double*, int, bool,
                                         hipStream_t);
-template hipError_t launch_zproj<double>(cplx<double>*, const Geom&, const cplx<double>*, const double*, int,
+template hipError_t launch_persist<float>(const float*, cplx<float>*, float*, float*, const Geom&, const cplx<float>*,
+                                          const cplx<float>*, const cplx<float>*, const double*, unsigned*, hipStream_t);
+
+template hipError_t launch_zproj<double>(cplx<double>*, const Geom&, const cplx<double>*, const double*, int, bool,
                                          hipStream_t);
 
 }  // namespace eq

@@ -141,6 +141,7 @@ void check_tune_parser() {
   const struct { const char* env; int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4, xsplit; } cases[] = {
       {"tx_y=16,tx_z=32,rw_x=4,chunk=32,radix16=2,schedule=5", 16, 32, 4, 32, 2, 5, 0, 0, 0},
       {"schedule=3 tc_zp=8", 0, 0, 0, 0, -1, 3, 8, 0, 0},
+      {"zp_e=4,schedule=3", 0, 0, 0, 0, -1, 3, 0, 0, 0},
       {"radix4=1,xsplit=2,,", 0, 0, 0, 0, -1, 0, 0, 1, 2},
       {"", 0, 0, 0, 0, -1, 0, 0, 0, 0},
       {",,,=,=5,tx_y=,unknown=3,tx_z", 0, 0, 0, 0, -1, 0, 0, 0, 0},
