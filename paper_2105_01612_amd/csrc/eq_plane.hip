@@ -373,38 +373,51 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__
 
 // One launch runs the three passes of a whole batch.  Workgroups claim work items in queue
 // order from a device-side counter.  Queue step s holds the forward planes of field s, the z
-// tiles of field s - 1 and the inverse planes of field s - 2, so an item only ever waits for
-// items earlier in the queue (claimed by workgroups that are running), and stages of
-// different fields overlap.  A z item of field b starts once every forward item of b is done,
+// tiles of field s - L and the inverse planes of field s - 2L (L >= 1, the lag: enough steps
+// that the items a wait depends on have mostly finished when it is claimed, with a whole grid
+// of workgroups in flight), so an item only ever waits for items earlier in the queue (claimed
+// by workgroups that are running), and stages of different fields overlap.  A z item of field b starts once every forward item of b is done,
 // an inverse item once every z item of b is done: per-field counters, raised after an item's
 // stores are complete and written back (agent-scope release), read before the item's loads
 // (agent-scope acquire).  Each item runs the same code as its pass kernel, so results are
 // bitwise those of the three launches; no output is written by an atomic.
+constexpr size_t kPsItemBytes = 16;   // LDS ahead of the bodies' LDS in the persistent launch
+
 struct PsArgs {
   int batch, nz;
   int gp, gt;               // planes per plane item, tiles per z item
   int nP, nZ;               // items per field of each plane stage, of the z stage
+  int lag;                  // queue steps between a field's stages
   unsigned* ctr;            // [0] queue head, [1] workgroups done, [2] a bounded wait gave up,
                             // [4 + b] forward items done of field b, [4 + batch + b] z items done
   unsigned spin_limit;      // polls of a dependency before giving up (the kernel always ends)
 };
 
-// Item q of the queue -> (stage 0 forward planes | 1 z tiles | 2 inverse planes, field, index).
+// Items in queue steps 0 .. s-1.
+__host__ __device__ __forceinline__ int ps_prefix(const PsArgs& a, int s) {
+  auto clampb = [&](int v) { return v < 0 ? 0 : (v > a.batch ? a.batch : v); };
+  return a.nP * clampb(s) + a.nZ * clampb(s - a.lag) + a.nP * clampb(s - 2 * a.lag);
+}
+
+// Item q of the queue -> (stage 0 forward planes | 1 z tiles | 2 inverse planes, field, index):
+// the step by bisection over the item counts, then forward, z and inverse items in that order.
 __device__ __forceinline__ void ps_decode(const PsArgs& a, int q, int& stage, int& b, int& j) {
-  for (int s = 0;; ++s) {
-    if (s < a.batch) {
-      if (q < a.nP) { stage = 0; b = s; j = q; return; }
-      q -= a.nP;
-    }
-    if (s >= 1 && s <= a.batch) {
-      if (q < a.nZ) { stage = 1; b = s - 1; j = q; return; }
-      q -= a.nZ;
-    }
-    if (s >= 2 && s <= a.batch + 1) {
-      if (q < a.nP) { stage = 2; b = s - 2; j = q; return; }
-      q -= a.nP;
-    }
+  int lo = 0, hi = a.batch + 2 * a.lag;          // ps_prefix(lo) <= q < ps_prefix(hi)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ps_prefix(a, mid) <= q) lo = mid;
+    else hi = mid;
   }
+  int r = q - ps_prefix(a, lo);
+  if (lo < a.batch) {
+    if (r < a.nP) { stage = 0; b = lo; j = r; return; }
+    r -= a.nP;
+  }
+  if (lo - a.lag >= 0 && lo - a.lag < a.batch) {
+    if (r < a.nZ) { stage = 1; b = lo - a.lag; j = r; return; }
+    r -= a.nZ;
+  }
+  stage = 2; b = lo - 2 * a.lag; j = r;
 }
 
 template <typename T, int N, int NT, typename FX, typename FY, typename FZ>
@@ -413,9 +426,12 @@ __global__ __launch_bounds__(NT) void k_persist(const T* __restrict__ in, cplx<T
                                                const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
                                                const cplx<T>* __restrict__ twz, const double* __restrict__ symu,
                                                T scale) {
+  // the claimed item sits in the first 16 bytes of the dynamic LDS and the bodies' LDS after
+  // it: a static __shared__ variable would put the dynamic LDS at its end (byte 4), and every
+  // 8-byte LDS access of the bodies would be misaligned
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  __shared__ int s_item;
+  int& s_item = *reinterpret_cast<int*>(smem_raw);
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw + kPsItemBytes);
   const int fplanes = 6 * a.nz;                       // planes of one field
   const int planes = a.batch * fplanes;
   const int ntile = zproj_tiles(za);
@@ -610,14 +626,18 @@ hipError_t persist_n(const T* in, cplx<T>* W2, T* out, T* removed, const Geom& g
   PsArgs a{};
   a.batch = g.batch;
   a.nz = g.nz;
-  a.gp = N * N >= 16384 ? 1 : 16384 / (N * N);          // about 64 K elements per plane item
-  a.gt = 1;
+  // items of about 64 K elements (a plane item) or one z tile; four times that from eight
+  // fields on, where the batch fills the device anyway and each item's claim, publish and
+  // L2 writeback and invalidate are paid a quarter as often
+  const int m = g.batch >= 8 ? 4 : 1;
+  a.gp = m * (N * N >= 16384 ? 1 : 16384 / (N * N));
+  a.gt = m;
   a.nP = (6 * g.nz + a.gp - 1) / a.gp;
   a.nZ = (zproj_tiles(za) + a.gt - 1) / a.gt;
   a.ctr = ctr;
   a.spin_limit = 1u << 18;
-  const size_t lds =
-      std::max(PlaneShape<T, N, N, NT, FX, FY>::lds_elems * sizeof(cplx<T>), zproj_lds(g, sizeof(T) == 8, TC));
+  const size_t lds = kPsItemBytes + std::max(PlaneShape<T, N, N, NT, FX, FY>::lds_elems * sizeof(cplx<T>),
+                                             zproj_lds(g, sizeof(T) == 8, TC));
   const void* k = reinterpret_cast<const void*>(&k_persist<T, N, NT, FX, FY, FZ>);
   static const hipError_t once = allow_lds(k, lds);
   if (once != hipSuccess) return once;
@@ -631,6 +651,9 @@ hipError_t persist_n(const T* in, cplx<T>* W2, T* out, T* removed, const Geom& g
   }();
   const int total = g.batch * (2 * a.nP + a.nZ);
   const int grid = std::max(1, std::min(cap, total));
+  // lag: one step, plus as many as the grid's items in flight cover
+  const int step_items = 2 * a.nP + a.nZ;
+  a.lag = 1 + (grid + step_items - 1) / step_items;
   const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
   hipLaunchKernelGGL((k_persist<T, N, NT, FX, FY, FZ>), dim3(grid), dim3(NT), lds, s, in, W2, out, removed, a, za, twx,
                      twy, twz, symu, scale);
