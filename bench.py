@@ -288,7 +288,7 @@ def run_serve(args):
     torch.cuda.synchronize()
     log(f"[bench] serve pools generated in {time.perf_counter() - t:.1f}s: {pool_n}")
     be = GpuBackend(pools, prec="fp32", op=args.op)
-    srv = Server(be, int(args.budget_gb * 2 ** 30))
+    srv = Server(be, int(args.budget_gb * 2 ** 30))          # smallest first, at most 8 in flight
     srv.warm(sizes)
     ns = wl.request_sizes(args.requests, seed=4000, sizes=sizes)
     rng = np.random.Generator(np.random.PCG64(4002))
@@ -300,13 +300,13 @@ def run_serve(args):
     res = srv.run([Request(i, int(n), float(a), f) for i, (n, a, f) in enumerate(zip(ns, arr, fields))])
     # admission policies at the same arrivals: in-flight cap and smallest-first
     policies = {}
-    for order, cap in (("fifo", 4), ("sjf", 4), ("sjf", 8), ("sjf", 16)):
+    for order, cap in (("fifo", None), ("fifo", 4), ("sjf", 4), ("sjf", 8), ("sjf", 16)):
         srv.order, srv.max_inflight = order, cap
         r = srv.run([Request(i, int(n), float(a), f) for i, (n, a, f) in enumerate(zip(ns, arr, fields))])
         policies[f"{order}_cap{cap}"] = {k: r[k] for k in ("requests_per_s", "p50_ms", "p99_ms", "mean_ms", "max_ms")}
         policies[f"{order}_cap{cap}"]["per_size"] = r["per_size"]
         log(f"[bench] serve 0.7x {order} cap {cap}: p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms")
-    srv.order, srv.max_inflight = "fifo", None
+    srv.order, srv.max_inflight = "sjf", 8
     over = srv.run([Request(i, int(n), float(a), f) for i, (n, a, f) in
                     enumerate(zip(ns, wl.poisson_arrivals(args.requests, 1.2 * sat["requests_per_s"], 4001), fields))])
     srv.close()
@@ -316,6 +316,8 @@ def run_serve(args):
                                    f"one grain per 16^3 voxels, FP32 {args.op.upper()}, graphs per slot, "
                                    f"budget {args.budget_gb} GiB"},
             "arrival_rate_per_s": lam, "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
+            "p99_ms_by_size": {k: v["p99_ms"] for k, v in res["per_size"].items()},
+            "policy": "smallest first, 8 in flight, 4 streams by size class",
             "saturated": sat, "at_0.7_saturation": res, "at_1.2_saturation": over,
             "policies_at_0.7_saturation": policies}
 
@@ -344,47 +346,113 @@ def run_grain_avg(args):
             "wall_s": time.perf_counter() - t0, "results": rows}
 
 
+def _inloop_rate(plan, a, b, stream, k):
+    """Asynchronous rate of k ping-pong projections (graph replays) and 40 synchronous calls;
+    `b` ends as P applied to the previous iterate."""
+    for _ in range(5):
+        plan.project(a, b)
+        plan.project(b, a)
+    stream.synchronize()
+    t = time.perf_counter()
+    for _ in range(k // 2):
+        plan.project(a, b)
+        plan.project(b, a)
+    stream.synchronize()
+    dt = (time.perf_counter() - t) / k
+    lat = []
+    for _ in range(40):
+        t1 = time.perf_counter()
+        plan.project(a, b)
+        stream.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    return dt, lat
+
+
 def run_inloop(args):
     """Repeated projection inside an iterative loop over one resident plan (Section 6: the
     filter as a step of an iterative reconstruction): each call replays the plan's captured
     hipGraph; x <- P(x) ping-pongs between two buffers.  Reports the asynchronous rate and
-    the synchronous per-call latency."""
+    the synchronous per-call latency; at 64^3 and 128^3 also the persistent single launch.
+    P is a projection, so the last buffer after every replay is P(x0) up to rounding: at 64^3
+    and 128^3 it is compared with the FP64 oracle's P(x0)."""
     import torch
     import paper_2105_01612_amd as eq
     from paper_2105_01612_amd import workload as wl
 
     rows = []
+    refs = {}
     for n in (64, 128, 256):
-        stream = torch.cuda.Stream()
-        with torch.cuda.stream(stream):
-            plan = eq.plan(n, op=args.op, prec="fp32", flags=["capture_graph"], stream=stream)
-            a = torch.from_numpy(wl.voronoi_field(wl.serving_spec(n, 0), dtype=np.float32)).cuda()
-            b = torch.empty_like(a)
-            for _ in range(5):
-                plan.project(a, b)
-                plan.project(b, a)
-            stream.synchronize()
-            k = 200 if n < 256 else 60
-            t = time.perf_counter()
-            for i in range(k // 2):
-                plan.project(a, b)
-                plan.project(b, a)
-            stream.synchronize()
-            dt = (time.perf_counter() - t) / k
-            lat = []
-            for i in range(40):
-                t1 = time.perf_counter()
-                plan.project(a, b)
-                stream.synchronize()
-                lat.append((time.perf_counter() - t1) * 1e3)
-            plan.destroy()
-        rows.append({"n": n, "projections_per_s": 1.0 / dt, "voxels_per_s": n ** 3 / dt,
-                     "p50_ms": statistics.median(lat), "p99_ms": float(np.percentile(lat, 99))})
-        log(f"[bench] inloop {n}^3: {1.0 / dt:.0f} projections/s, sync p50 {rows[-1]['p50_ms']:.3f} ms")
-    return {"metric": "repeated in-loop projections (graph replay, one plan)", "value": rows[1]["projections_per_s"],
+        x0 = wl.voronoi_field(wl.serving_spec(n, 0), dtype=np.float32)
+        for persistent in ((False, True) if n < 256 else (False,)):
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                flags = ["capture_graph"] + (["persistent"] if persistent else [])
+                plan = eq.plan(n, op=args.op, prec="fp32", flags=flags, stream=stream)
+                a = torch.from_numpy(x0).cuda()
+                b = torch.empty_like(a)
+                dt, lat = _inloop_rate(plan, a, b, stream, 200 if n < 256 else 60)
+                plan.destroy()
+                final = b.cpu().numpy()
+            row = {"n": n, "persistent": persistent, "replays": (200 if n < 256 else 60) + 50,
+                   "projections_per_s": 1.0 / dt, "voxels_per_s": n ** 3 / dt,
+                   "p50_ms": statistics.median(lat), "p99_ms": float(np.percentile(lat, 99))}
+            if n < 256:
+                if n not in refs:
+                    import oracle
+
+                    refs[n] = oracle.project(x0.astype(np.float64), args.op)[0]
+                rel, mab = frob_err(final[None], refs[n][None])
+                row["error_vs_oracle"] = {"rel_l2": rel, "max_abs_mpa": mab, "tol": 1e-5}
+            rows.append(row)
+            log(f"[bench] inloop {n}^3{' persistent' if persistent else ''}: {1.0 / dt:.0f} projections/s, "
+                f"sync p50 {rows[-1]['p50_ms']:.3f} ms"
+                + (f", oracle rel-L2 {row['error_vs_oracle']['rel_l2']:.2e}" if "error_vs_oracle" in row else ""))
+    head = next(r for r in rows if r["n"] == 128 and not r["persistent"])
+    return {"metric": "repeated in-loop projections (graph replay, one plan)", "value": head["projections_per_s"],
             "unit": "projections/s (128^3 FP32)", "higher_is_better": True, "n_gpus": 1,
             "data": "synthetic: serving pool field 0 per size", "config": {"workload": "inloop", "op": args.op},
+            "error_vs_oracle_tol": 1e-5,
             "results": rows}
+
+
+def run_persistent(args):
+    """Batches of 64 fields (64^3 and 128^3, 300 grains each, seeds 300..363) projected by the
+    per-pass three-pass schedule (its default z stage, and the four-element z stage the
+    persistent launch uses) and by one persistent launch; ms per batch over `steps` calls."""
+    import torch
+    import paper_2105_01612_amd as eq
+    from paper_2105_01612_amd import workload as wl
+
+    rows = []
+    for n in (64, 128):
+        S = np.stack([wl.voronoi_field(sp, dtype=np.float32) for sp in wl.batched_specs(n=n)])
+        x = torch.from_numpy(S).cuda()
+        out = torch.empty_like(x)
+        rem = torch.empty_like(x)
+        for label, flags, tune in (("three_pass", [], dict(schedule=3)), ("three_pass_zp4", [], dict(schedule=3, zp_e=4)),
+                                   ("persistent", ["persistent"], None)):
+            plan = eq.plan(n, batch=64, op=args.op, prec="fp32", flags=flags)
+            if tune:
+                plan.tune(**tune)
+            for _ in range(args.warmup):
+                plan.project(x, out, rem)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                plan.project(x, out, rem)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) / args.steps * 1e3
+            plan.destroy()
+            rows.append({"n": n, "batch": 64, "path": label, "ms_per_batch": ms, "voxels_per_s": 64 * n ** 3 / (ms * 1e-3),
+                         "hbm_frac_168B": 64 * n ** 3 * 168 / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)})
+            log(f"[bench] 64 x {n}^3 {label}: {ms:.3f} ms")
+        del x, out, rem
+        torch.cuda.empty_cache()
+    head = next(r for r in rows if r["n"] == 64 and r["path"] == "persistent")
+    return {"metric": "batched projection, one persistent launch vs three launches", "value": head["voxels_per_s"],
+            "unit": "voxels/s (64 x 64^3 FP32, persistent)", "higher_is_better": True, "n_gpus": 1,
+            "data": "synthetic: 64 Voronoi fields per size, 300 grains, seeds 300-363",
+            "config": {"workload": "persistent", "op": args.op}, "results": rows}
 
 
 def main():
@@ -394,7 +462,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "small", "largest", "gb_heavy", "batched", "serve", "grain_avg",
-                             "inloop"])
+                             "inloop", "persistent"])
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for slots")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
@@ -433,6 +501,9 @@ def main():
         return
     if args.workload == "inloop":
         print(json.dumps(run_inloop(args)), flush=True)
+        return
+    if args.workload == "persistent":
+        print(json.dumps(run_persistent(args)), flush=True)
         return
     if args.copy_calibration:
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")

@@ -1,14 +1,17 @@
 """Continuous-batching request loop for equilibrium projections on one GPU.
 
 Requests (one stress field each, any supported grid size) arrive over time.  The
-server keeps *slots* per size class: a slot is a libeq plan with its own stream
-and captured hipGraph, plus device input/output buffers.  A request is admitted
-as soon as a slot of its class is free, or a new slot fits the HBM budget
-(eq_plan_footprint + buffers), evicting idle slots of other classes if needed.
-Admitted work runs asynchronously on the slot's stream, so requests of different
-slots overlap on the device; completions are found by polling events, and every
-completion frees a slot for the next waiting request (no head-of-line blocking
-across classes).  Inputs are taken from device-resident pools, as if produced by
+server keeps *slots* per size class: a slot is a libeq plan with a captured
+hipGraph, plus device input/output buffers.  A request is admitted as soon as a
+slot of its class is free, or a new slot fits the HBM budget (eq_plan_footprint +
+buffers), evicting idle slots of other classes if needed.  Admitted work runs
+asynchronously on its slot's stream; the backend keeps a small pool of streams (as
+many as the device has hardware queues) and gives each size class the stream of
+its rank among the sizes, so a small request never waits in a stream behind a large
+one, while requests on different streams overlap on the device.  Completions are
+found by polling events, and every completion frees a slot for the next waiting
+request (no head-of-line blocking across classes).  By default the smallest waiting
+field is admitted first and at most eight requests run at once.  Inputs are taken from device-resident pools, as if produced by
 an upstream GPU stage; the copy into the slot is part of the request's service.
 
 The executor is a backend object, so the admission and bookkeeping logic also runs
@@ -50,10 +53,21 @@ class Slot:
         self.last_used = 0.0
 
 
-class GpuBackend:
-    """libeq executor: one plan (own stream, graph capture) and two buffers per slot."""
+def stream_of_size(n: int, sizes, streams: int) -> int:
+    """Stream index of size class n: its rank among `sizes`, scaled onto `streams` streams
+    (smallest sizes on stream 0, the largest alone on the last one when there are enough)."""
+    order = sorted(set(int(x) for x in sizes))
+    if n not in order:
+        order = sorted(set(order) | {int(n)})
+    return min(streams - 1, order.index(int(n)) * streams // len(order))
 
-    def __init__(self, pools: Dict[int, "object"], prec: str = "fp32", op: str = "ddo", h: float = 1.0):
+
+class GpuBackend:
+    """libeq executor: one plan (graph capture) and two buffers per slot; slots share a pool of
+    `streams` streams by size class (see stream_of_size)."""
+
+    def __init__(self, pools: Dict[int, "object"], prec: str = "fp32", op: str = "ddo", h: float = 1.0,
+                 streams: int = 4):
         import torch
 
         import paper_2105_01612_amd as eq
@@ -62,6 +76,8 @@ class GpuBackend:
         self.pools = pools            # n -> device tensor (k, 6, n, n, n)
         self.prec, self.op, self.h = prec, op, h
         self.dtype = torch.float32 if prec == "fp32" else torch.float64
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, int(streams)))]
+        self.sizes = sorted(int(n) for n in pools)
 
     def slot_bytes(self, n: int) -> int:
         field = 6 * n ** 3 * (4 if self.prec == "fp32" else 8)
@@ -69,7 +85,7 @@ class GpuBackend:
 
     def create(self, n: int):
         torch = self.torch
-        stream = torch.cuda.Stream()
+        stream = self.streams[stream_of_size(n, self.sizes, len(self.streams))]
         plan = self.eq.plan(n, op=self.op, prec=self.prec, h=self.h, flags=["capture_graph"], stream=stream)
         with torch.cuda.stream(stream):
             inp = torch.empty((6, n, n, n), dtype=self.dtype, device="cuda")
@@ -93,16 +109,19 @@ class GpuBackend:
         h["stream"].synchronize()
         h["plan"].destroy()
         del h["inp"], h["out"]
+        # return the slot's buffers to the device, so that the budget's count of the HBM in use
+        # matches what the next plan allocation finds free
+        self.torch.cuda.empty_cache()
 
 
 class Server:
     """max_inflight caps the requests running at once (None: as many as slots allow); with a
-    cap, requests queue on the host and the device runs fewer, shorter-lived streams, which
-    bounds how long a small request shares the GPU with large ones.  order: "fifo" admits in
-    arrival order, "sjf" admits the smallest waiting field first."""
+    cap, requests queue on the host, which bounds how long a small request shares the GPU with
+    large ones.  order: "fifo" admits in arrival order, "sjf" (the default) admits the smallest
+    waiting field first."""
 
     def __init__(self, backend, budget_bytes: int, max_slots_per_class: int = 8,
-                 max_inflight: Optional[int] = None, order: str = "fifo"):
+                 max_inflight: Optional[int] = 8, order: str = "sjf"):
         if order not in ("fifo", "sjf"):
             raise ValueError("order must be 'fifo' or 'sjf'")
         self.backend = backend

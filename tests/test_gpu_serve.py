@@ -1,6 +1,8 @@
 """Serving on the GPU: every request's result is the same alone and in the mix
 (bitwise: same kernels, same shapes, no atomics on the output path), results match
-the oracle, and the budget holds while requests queue and overlap."""
+the oracle, and the budget holds while requests queue and overlap.  The small classes
+run many requests; the serving workload's own classes 96^3 to 384^3 each run alone and
+in a mix with the others, and each class is checked against the oracle once."""
 import numpy as np
 import pytest
 
@@ -8,18 +10,40 @@ import oracle as O
 from paper_2105_01612_amd import workload as wl
 
 pytestmark = pytest.mark.gpu
+W6 = np.array([1, 1, 1, 2, 2, 2.0]).reshape(6, 1, 1, 1)
+
+
+def frob_rel(got, ref):
+    d = got.astype(np.float64) - ref
+    return float(np.sqrt(np.sum(W6 * d * d) / np.sum(W6 * ref * ref)))
+
+
+def _pools(sizes, per_class, grains_of):
+    import torch
+
+    host = {n: np.stack([wl.voronoi_field(wl.FieldSpec((n, n, n), grains=grains_of(n), sigma_grain=100.0,
+                                                      sigma_noise=5.0, seed=4100 + 7 * n + j), dtype=np.float32)
+                         for j in range(per_class)]) for n in sizes}
+    pools = {n: torch.from_numpy(a).cuda() for n, a in host.items()}
+    torch.cuda.synchronize()
+    return host, pools
+
+
+def _alone(pools, budget, r):
+    from paper_2105_01612_amd.serve import GpuBackend, Request, Server
+
+    out = {}
+    s1 = Server(GpuBackend(pools, prec="fp32", op="ddo"), budget)
+    s1.run([Request(r.rid, r.n, 0.0, r.field)], on_complete=lambda q, o: out.__setitem__(q.rid, o.cpu().numpy().copy()))
+    s1.close()
+    return out[r.rid]
 
 
 def test_alone_equals_mix_and_oracle():
-    import torch
     from paper_2105_01612_amd.serve import GpuBackend, Request, Server
 
     sizes = (32, 48, 64)
-    host = {n: np.stack([wl.voronoi_field(wl.FieldSpec((n, n, n), grains=max(2, n ** 3 // 16 ** 3),
-                                                      sigma_grain=100.0, sigma_noise=5.0, seed=4100 + 7 * n + j),
-                                          dtype=np.float32) for j in range(2)]) for n in sizes}
-    pools = {n: torch.from_numpy(a).cuda() for n, a in host.items()}
-    torch.cuda.synchronize()
+    host, pools = _pools(sizes, 2, lambda n: max(2, n ** 3 // 16 ** 3))
     be = GpuBackend(pools, prec="fp32", op="ddo")
     budget = be.slot_bytes(64) + be.slot_bytes(48) + 2 * be.slot_bytes(32)
     arr = wl.poisson_arrivals(40, 4000.0, seed=11)
@@ -31,14 +55,39 @@ def test_alone_equals_mix_and_oracle():
     assert stats["completed"] == 40 and srv.peak_used <= budget
     srv.close()
     for r in reqs[:12]:
-        alone = {}
-        s1 = Server(GpuBackend(pools, prec="fp32", op="ddo"), budget)
-        s1.run([Request(r.rid, r.n, 0.0, r.field)],
-               on_complete=lambda q, out: alone.__setitem__(q.rid, out.cpu().numpy().copy()))
-        s1.close()
-        assert np.array_equal(alone[r.rid], mix[r.rid]), r
+        assert np.array_equal(_alone(pools, budget, r), mix[r.rid]), r
     for r in reqs[:3]:
         ref, _ = O.project(host[r.n][r.field].astype(np.float64), "ddo")
-        w = np.array([1, 1, 1, 2, 2, 2.0]).reshape(6, 1, 1, 1)
-        d = mix[r.rid] - ref
-        assert np.sqrt(np.sum(w * d * d) / np.sum(w * ref * ref)) <= 1e-5
+        assert frob_rel(mix[r.rid], ref) <= 1e-5
+
+
+def test_serving_classes_alone_equal_mix_and_oracle():
+    """The serving workload's classes 96, 128, 192, 256 and 384 (one grain per 16^3 voxels is
+    not needed for this check: a few grains per field), all requests arriving together so
+    that they overlap on the device, against each request alone and against the oracle."""
+    import torch
+    from paper_2105_01612_amd.serve import GpuBackend, Request, Server
+
+    sizes = (96, 128, 192, 256, 384)
+    host, pools = _pools(sizes, 1, lambda n: 24)
+    be = GpuBackend(pools, prec="fp32", op="ddo")
+    budget = sum(be.slot_bytes(n) for n in sizes)
+    order = [384, 96, 256, 128, 192, 96, 384, 128]
+    reqs = [Request(i, n, 0.0, 0) for i, n in enumerate(order)]
+    mix = {}
+    srv = Server(be, budget, max_slots_per_class=1)
+    stats = srv.run(reqs, on_complete=lambda r, out: mix.__setitem__(r.rid, out.cpu().numpy().copy()))
+    assert stats["completed"] == len(reqs) and srv.peak_used <= budget
+    assert set(stats["per_size"]) == {str(n) for n in sizes}
+    srv.close()
+    torch.cuda.empty_cache()
+    seen = set()
+    for r in reqs:
+        if r.n in seen:
+            assert np.array_equal(mix[r.rid], mix[next(q.rid for q in reqs if q.n == r.n)])
+            continue
+        seen.add(r.n)
+        assert np.array_equal(_alone(pools, budget, r), mix[r.rid]), r.n
+        ref, _ = O.project(host[r.n][0].astype(np.float64), "ddo")
+        assert frob_rel(mix[r.rid], ref) <= 1e-5, r.n
+        del ref
