@@ -651,9 +651,10 @@ eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out
   return EQ_OK;
 }
 
-bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+// [a, a + abytes) and [b, b + bbytes) share a byte
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
   const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-  return x < y + bytes && y < x + bytes;
+  return x < y + bbytes && y < x + abytes;
 }
 
 struct DeviceGuard {
@@ -773,9 +774,9 @@ eq_status eq_project(eq_plan_t p, const void* s_in, void* s_eq, void* s_removed)
   if (!p) return fail(EQ_ERR_ARG, "null plan");
   if (!s_in || !s_eq) return fail(EQ_ERR_ARG, "null input or output pointer");
   const size_t bytes = (size_t)p->g.batch * 6 * field_elems(p) * elem_size(&p->desc);
-  if (s_removed && (ranges_overlap(s_removed, s_in, bytes) || ranges_overlap(s_removed, s_eq, bytes)))
+  if (s_removed && (ranges_overlap(s_removed, bytes, s_in, bytes) || ranges_overlap(s_removed, bytes, s_eq, bytes)))
     return fail(EQ_ERR_ARG, "s_removed overlaps s_in or s_eq");
-  if (s_eq != s_in && ranges_overlap(s_eq, s_in, bytes))
+  if (s_eq != s_in && ranges_overlap(s_eq, bytes, s_in, bytes))
     return fail(EQ_ERR_ARG, "s_eq partially overlaps s_in");
   DeviceGuard dg(p->device);
   const bool fp64 = p->desc.prec == EQ_FP64;
@@ -821,9 +822,9 @@ eq_status eq_project_embedded(eq_plan_t p, const eq_embed* em, const void* s_in,
   e.nx0 = em->nx0; e.ny0 = em->ny0; e.ox = em->ox; e.oy = em->oy; e.on = true;
   const size_t n = (size_t)g.batch * 6 * g.nz * e.ny0 * e.nx0;
   const size_t bytes = n * elem_size(&p->desc);
-  if (s_removed && (ranges_overlap(s_removed, s_in, bytes) || ranges_overlap(s_removed, s_eq, bytes)))
+  if (s_removed && (ranges_overlap(s_removed, bytes, s_in, bytes) || ranges_overlap(s_removed, bytes, s_eq, bytes)))
     return fail(EQ_ERR_ARG, "s_removed overlaps s_in or s_eq");
-  if (s_eq != s_in && ranges_overlap(s_eq, s_in, bytes)) return fail(EQ_ERR_ARG, "s_eq partially overlaps s_in");
+  if (s_eq != s_in && ranges_overlap(s_eq, bytes, s_in, bytes)) return fail(EQ_ERR_ARG, "s_eq partially overlaps s_in");
   DeviceGuard dg(p->device);
   const bool fp64 = p->desc.prec == EQ_FP64;
   p->last_removed = s_removed != nullptr;
@@ -838,8 +839,8 @@ eq_status eq_residual(eq_plan_t p, const void* s, double* norms_host, void* div_
   if (!p) return fail(EQ_ERR_ARG, "null plan");
   if (!s || !norms_host) return fail(EQ_ERR_ARG, "null field or norms pointer");
   const size_t es = elem_size(&p->desc);
-  if (div_out && ranges_overlap(div_out, s, (size_t)p->g.batch * 6 * field_elems(p) * es))
-    return fail(EQ_ERR_ARG, "div_out overlaps the field");
+  const size_t fbytes = (size_t)p->g.batch * field_elems(p) * es;     // one component of every field
+  if (div_out && ranges_overlap(div_out, 3 * fbytes, s, 6 * fbytes)) return fail(EQ_ERR_ARG, "div_out overlaps the field");
   DeviceGuard dg(p->device);
   return p->desc.prec == EQ_FP64 ? run_residual<double>(p, s, norms_host, div_out)
                                  : run_residual<float>(p, s, norms_host, div_out);

@@ -273,6 +273,11 @@ struct DArgs {
   double inv2h;
 };
 
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T x, y;
+};
+
 // Element e of component c of one field: a raw buffer load when every component's byte
 // range fits the 32-bit offset (the six resources sit in SGPRs and one 32-bit offset per
 // neighbour serves all six components), else a plain load.
@@ -286,6 +291,23 @@ struct FieldReader {
       f[c] = F + c * M;
       if constexpr (BUF) r[c] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f[c]), 0, (int)(M * sizeof(T)), kBufWord3);
     }
+  }
+  // elements e and e + 1 (e even: 8-byte aligned in FP32, 16-byte in FP64), unconverted
+  __device__ __forceinline__ Pair<T> raw2(int c, size_t e) const {
+    Pair<T> v;
+    if constexpr (BUF) {
+      const unsigned off = (unsigned)e * (unsigned)sizeof(T);
+      if constexpr (sizeof(T) == 4) {
+        const auto r2 = __builtin_amdgcn_raw_buffer_load_b64(r[c], off, 0, 0);
+        __builtin_memcpy(&v, &r2, sizeof(v));
+      } else {
+        const auto r2 = __builtin_amdgcn_raw_buffer_load_b128(r[c], off, 0, 0);
+        __builtin_memcpy(&v, &r2, sizeof(v));
+      }
+    } else {
+      v = *reinterpret_cast<const Pair<T>*>(f[c] + e);
+    }
+    return v;
   }
   // the stored value, unconverted
   __device__ __forceinline__ T raw(int c, size_t e) const {
@@ -425,6 +447,177 @@ __global__ __launch_bounds__(kRedThreads) void k_div_ddo(const T* __restrict__ S
       if (kAhead) {
 #pragma unroll
         for (int k = 0; k < 30; ++k) cur[k] = nxt[k];
+      }
+      a2m = a2c; a3m = a3c; a4m = a4c;
+      a2c = a2p; a3c = a3p; a4c = a4p;
+      b2m = b2c; b3m = b3c; b4m = b4c;
+      b2c = b2p; b3c = b3p; b4c = b4p;
+    }
+  }
+  block_reduce_record(acc, sh);
+  if (threadIdx.x == 0) {
+    double* pp = partials + ((size_t)b * gridDim.x + blockIdx.x) * kRedWidth;
+#pragma unroll
+    for (int k = 0; k < kRedWidth; ++k) pp[k] = acc[k];
+  }
+}
+
+// The same divergence and record for FP64 fields with nx a multiple of 128, with two x
+// columns per lane: a wavefront spans 128 columns of rows y and y + 1, each load brings two
+// values (16 bytes per lane, half the instructions), and the x neighbours of a lane's pair
+// are the next lanes' values (a lane shuffle; lanes 0 and 63 load them when the wavefront
+// does not span the whole row).  The four wavefronts of a workgroup take four consecutive
+// row pairs, so the outer rows y - 1 and y + 2 of all but two of them are rows the workgroup
+// reads itself.  Per-voxel values are those of k_div_ddo bit for bit.  (In FP32 the
+// one-column kernel is faster: it holds 12 wavefronts per CU against this kernel's 8.)
+struct DvArgs {
+  int nx, ny, nz;
+  int tiles_x;           // nx / 128
+  int tiles;             // tiles_x x groups of 8 rows
+  int zc;                // z chunks: a work item is (tile, z chunk)
+  double inv2h;
+};
+
+template <typename T>
+__device__ __forceinline__ T lane_from(T v, int src) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+  } else {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  }
+}
+
+template <typename T, bool BUF>
+__global__ __launch_bounds__(kRedThreads) void k_div_ddo2(const T* __restrict__ S, T* __restrict__ div,
+                                                          double* __restrict__ partials, DvArgs a) {
+  __shared__ double sh[kRedWidth * kRedThreads];
+  using P2 = Pair<T>;
+  const int b = blockIdx.y;
+  const size_t M = (size_t)a.nx * a.ny * a.nz;
+  const size_t sz = (size_t)a.nx * a.ny;
+  const FieldReader<T, BUF> F(S + (size_t)b * 6 * M, M);
+  double acc[kRedWidth];
+#pragma unroll
+  for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+  // component sums about the field's first voxel, as in k_div_ddo
+  const double sh0 = uniform_f64(F(0, 0)), sh1 = uniform_f64(F(1, 0)), sh2 = uniform_f64(F(2, 0));
+  const double sh3 = uniform_f64(F(3, 0)), sh4 = uniform_f64(F(4, 0)), sh5 = uniform_f64(F(5, 0));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int src_l = (lane + 63) & 63, src_r = (lane + 1) & 63;
+  // lanes 0 and 63 take their outer neighbour from memory unless the wavefront spans the row
+  const bool edge_l = a.tiles_x > 1 && lane == 0, edge_r = a.tiles_x > 1 && lane == 63;
+  const int items = a.tiles * a.zc;
+  const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
+  for (int it = lb; it < items; it += gridDim.x) {
+    const int tile = it % a.tiles, zi = it / a.tiles;
+    const int x0 = (tile % a.tiles_x) * 128 + 2 * lane;
+    const int y = (tile / a.tiles_x) * 8 + 2 * w;                   // even; ny is even
+    const int z0 = (int)(((long)zi * a.nz) / a.zc), z1 = (int)(((long)(zi + 1) * a.nz) / a.zc);
+    if (y >= a.ny || z0 >= z1) continue;                            // uniform in the wavefront
+    const size_t ca = (size_t)y * a.nx + x0, cb = ca + a.nx;
+    const size_t ym = (y == 0) ? ca + sz - a.nx : ca - a.nx;
+    const size_t yq = (y + 2 == a.ny) ? ca + 2 * a.nx - sz : ca + 2 * a.nx;
+    const long dl = (x0 == 0) ? (long)a.nx - 1 : -1;                // column x0 - 1
+    const long dr = (x0 + 2 == a.nx) ? 2 - (long)a.nx : 2;          // column x0 + 2
+    // x neighbours of a pair: column x0 - 1 is the previous lane's second value, x0 + 2 the
+    // next lane's first
+    auto nb_l = [&](const P2& v, int c, size_t q) -> T {
+      const T s = lane_from<T>(v.y, src_l);
+      return edge_l ? F.raw(c, q + dl) : s;
+    };
+    auto nb_r = [&](const P2& v, int c, size_t q) -> T {
+      const T s = lane_from<T>(v.x, src_r);
+      return edge_r ? F.raw(c, q + dr) : s;
+    };
+    const size_t pm = (size_t)(z0 == 0 ? a.nz - 1 : z0 - 1) * sz;
+    const size_t p0 = (size_t)z0 * sz;
+    // S33, S23, S13 (slots 2, 3, 4) of planes z - 1 and z, rows a and b
+    P2 a2m = F.raw2(2, pm + ca), a3m = F.raw2(3, pm + ca), a4m = F.raw2(4, pm + ca);
+    P2 b2m = F.raw2(2, pm + cb), b3m = F.raw2(3, pm + cb), b4m = F.raw2(4, pm + cb);
+    P2 a2c = F.raw2(2, p0 + ca), a3c = F.raw2(3, p0 + ca), a4c = F.raw2(4, p0 + ca);
+    P2 b2c = F.raw2(2, p0 + cb), b3c = F.raw2(3, p0 + cb), b4c = F.raw2(4, p0 + cb);
+    // one plane step: S11, S22, S12 of rows a and b; S12, S22, S23 of the outer rows y - 1 and
+    // y + 2; S33, S23, S13 of rows a and b on the next plane.  FP32 fields load the step after
+    // next while the current one is evaluated.
+    auto load_step = [&](int z, P2* v) {
+      const size_t p = (size_t)z * sz;
+      const size_t pn = (size_t)(z + 1 == a.nz ? 0 : z + 1) * sz;
+      v[0] = F.raw2(0, p + ca); v[1] = F.raw2(1, p + ca); v[2] = F.raw2(5, p + ca);
+      v[3] = F.raw2(0, p + cb); v[4] = F.raw2(1, p + cb); v[5] = F.raw2(5, p + cb);
+      v[6] = F.raw2(5, p + ym); v[7] = F.raw2(1, p + ym); v[8] = F.raw2(3, p + ym);
+      v[9] = F.raw2(5, p + yq); v[10] = F.raw2(1, p + yq); v[11] = F.raw2(3, p + yq);
+      v[12] = F.raw2(2, pn + ca); v[13] = F.raw2(3, pn + ca); v[14] = F.raw2(4, pn + ca);
+      v[15] = F.raw2(2, pn + cb); v[16] = F.raw2(3, pn + cb); v[17] = F.raw2(4, pn + cb);
+    };
+    constexpr bool kAhead = sizeof(T) == 4;     // (FP64 only in use: no look-ahead)
+    P2 cur[18], nxt[18];
+    load_step(z0, cur);
+    for (int z = z0; z < z1; ++z) {
+      const size_t p = (size_t)z * sz;
+      if (kAhead) {
+        if (z + 1 < z1) load_step(z + 1, nxt);
+      } else if (z > z0) {
+        load_step(z, cur);
+      }
+      const size_t qa = p + ca, qb = p + cb;
+      const P2 a0 = cur[0], a1 = cur[1], a5 = cur[2], b0 = cur[3], b1 = cur[4], b5 = cur[5];
+      const P2 a2p = cur[12], a3p = cur[13], a4p = cur[14], b2p = cur[15], b3p = cur[16], b4p = cur[17];
+      // x neighbours of S11, S12 (rows a, b; this plane) and S13 (rows a, b; this plane)
+      const double a0l = nb_l(a0, 0, qa), a0r = nb_r(a0, 0, qa), b0l = nb_l(b0, 0, qb), b0r = nb_r(b0, 0, qb);
+      const double a5l = nb_l(a5, 5, qa), a5r = nb_r(a5, 5, qa), b5l = nb_l(b5, 5, qb), b5r = nb_r(b5, 5, qb);
+      const double a4l = nb_l(a4c, 4, qa), a4r = nb_r(a4c, 4, qa), b4l = nb_l(b4c, 4, qb), b4r = nb_r(b4c, 4, qb);
+      auto D = [](T v) { return (double)v; };
+      double r[2][2][3];      // [column][row a, b][component]
+      // column x0: x neighbours x0 + 1 (the pair's second value) and x0 - 1
+      r[0][0][0] = ((D(a0.y) - a0l) + (D(b5.x) - D(cur[6].x)) + (D(a4p.x) - D(a4m.x))) * a.inv2h;
+      r[0][0][1] = ((D(a5.y) - a5l) + (D(b1.x) - D(cur[7].x)) + (D(a3p.x) - D(a3m.x))) * a.inv2h;
+      r[0][0][2] = ((D(a4c.y) - a4l) + (D(b3c.x) - D(cur[8].x)) + (D(a2p.x) - D(a2m.x))) * a.inv2h;
+      r[0][1][0] = ((D(b0.y) - b0l) + (D(cur[9].x) - D(a5.x)) + (D(b4p.x) - D(b4m.x))) * a.inv2h;
+      r[0][1][1] = ((D(b5.y) - b5l) + (D(cur[10].x) - D(a1.x)) + (D(b3p.x) - D(b3m.x))) * a.inv2h;
+      r[0][1][2] = ((D(b4c.y) - b4l) + (D(cur[11].x) - D(a3c.x)) + (D(b2p.x) - D(b2m.x))) * a.inv2h;
+      // column x0 + 1: x neighbours x0 + 2 and x0 (the pair's first value)
+      r[1][0][0] = ((a0r - D(a0.x)) + (D(b5.y) - D(cur[6].y)) + (D(a4p.y) - D(a4m.y))) * a.inv2h;
+      r[1][0][1] = ((a5r - D(a5.x)) + (D(b1.y) - D(cur[7].y)) + (D(a3p.y) - D(a3m.y))) * a.inv2h;
+      r[1][0][2] = ((a4r - D(a4c.x)) + (D(b3c.y) - D(cur[8].y)) + (D(a2p.y) - D(a2m.y))) * a.inv2h;
+      r[1][1][0] = ((b0r - D(b0.x)) + (D(cur[9].y) - D(a5.y)) + (D(b4p.y) - D(b4m.y))) * a.inv2h;
+      r[1][1][1] = ((b5r - D(b5.x)) + (D(cur[10].y) - D(a1.y)) + (D(b3p.y) - D(b3m.y))) * a.inv2h;
+      r[1][1][2] = ((b4r - D(b4c.x)) + (D(cur[11].y) - D(a3c.y)) + (D(b2p.y) - D(b2m.y))) * a.inv2h;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double ma = r[k][0][0] * r[k][0][0] + r[k][0][1] * r[k][0][1] + r[k][0][2] * r[k][0][2];
+        const double mb = r[k][1][0] * r[k][1][0] + r[k][1][1] * r[k][1][1] + r[k][1][2] * r[k][1][2];
+        acc[0] += ma + mb;
+        acc[1] = fmax(acc[1], fmax(ma, mb));
+      }
+      {
+        // component statistics of the four voxels (slots 0 .. 5), about the shifts
+        const double v[6][4] = {{D(a0.x), D(a0.y), D(b0.x), D(b0.y)},     {D(a1.x), D(a1.y), D(b1.x), D(b1.y)},
+                                {D(a2c.x), D(a2c.y), D(b2c.x), D(b2c.y)}, {D(a3c.x), D(a3c.y), D(b3c.x), D(b3c.y)},
+                                {D(a4c.x), D(a4c.y), D(b4c.x), D(b4c.y)}, {D(a5.x), D(a5.y), D(b5.x), D(b5.y)}};
+        const double shv[6] = {sh0, sh1, sh2, sh3, sh4, sh5};
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double d = v[c][k] - shv[c];
+            acc[2 + c] += d;
+            acc[8 + c] += d * d;
+          }
+      }
+      if (div) {
+        T* o = div + (size_t)b * 3 * M;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          *reinterpret_cast<P2*>(o + c * M + qa) = P2{(T)r[0][0][c], (T)r[1][0][c]};
+          *reinterpret_cast<P2*>(o + c * M + qb) = P2{(T)r[0][1][c], (T)r[1][1][c]};
+        }
+      }
+      if (kAhead) {
+#pragma unroll
+        for (int k = 0; k < 18; ++k) cur[k] = nxt[k];
       }
       a2m = a2c; a3m = a3c; a4m = a4c;
       a2c = a2p; a3c = a3p; a4c = a4p;
@@ -851,15 +1044,25 @@ bool div_ddo_buf(const Geom& g) {
   return (double)g.nx * g.ny * g.nz * sizeof(T) < 2147483648.0;
 }
 
-// Workgroups of k_div_ddo<T, BUF> the device holds at once (CUs x resident workgroups per CU).
-template <typename T, bool BUF>
+// The two-column kernel serves FP64 fields with nx a multiple of 128 (one wavefront spans
+// 128 columns).
+template <typename T>
+bool div_ddo_pairs(const Geom& g) {
+  return sizeof(T) == 8 && g.nx % 128 == 0;
+}
+
+// Workgroups of the DDO divergence kernel the device holds at once (CUs x resident
+// workgroups per CU).
+template <typename T, bool BUF, bool PAIRS>
 int div_ddo_capacity() {
   static const int cap = [] {
     int dev = 0, cus = 0, per = 0;
+    const void* k = nullptr;
+    if constexpr (PAIRS) k = reinterpret_cast<const void*>(&k_div_ddo2<T, BUF>);
+    else k = reinterpret_cast<const void*>(&k_div_ddo<T, BUF>);
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_div_ddo<T, BUF>),
-                                                     kRedThreads, 0) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kRedThreads, 0) != hipSuccess)
       return 0;
     return cus * per;
   }();
@@ -867,7 +1070,38 @@ int div_ddo_capacity() {
 }
 template <typename T>
 int div_ddo_cap(const Geom& g) {
-  return div_ddo_buf<T>(g) ? div_ddo_capacity<T, true>() : div_ddo_capacity<T, false>();
+  if constexpr (sizeof(T) == 8) {
+    if (div_ddo_pairs<T>(g))
+      return div_ddo_buf<T>(g) ? div_ddo_capacity<T, true, true>() : div_ddo_capacity<T, false, true>();
+  }
+  return div_ddo_buf<T>(g) ? div_ddo_capacity<T, true, false>() : div_ddo_capacity<T, false, false>();
+}
+
+// z chunks per work item: the count that wastes least of the resident capacity G for one
+// field (the fewest items on ties), at least 8 planes per march where possible.
+static int div_ddo_chunks(int tiles, int nz, int G) {
+  const int zmax = nz >= 16 ? nz / 8 : 1;
+  double best = -1.0;
+  int zc = 1;
+  for (int c = 1; c <= zmax; ++c) {
+    const long items = (long)tiles * c;
+    const long grid = items < G ? items : G;
+    const long rounds = (items + grid - 1) / grid;
+    const double eff = ((double)tiles * nz / G) / ((double)rounds * ((nz + c - 1) / c));
+    if (eff > best + 1e-9) { best = eff; zc = c; }
+  }
+  return zc;
+}
+
+// Two-column shape: tiles of 128 columns by 8 rows (the last row group may be short).
+static DvArgs div_ddo2_shape(const Geom& g, int nblk_max, double h, int cap) {
+  DvArgs a{};
+  a.nx = g.nx; a.ny = g.ny; a.nz = g.nz;
+  a.tiles_x = g.nx / 128;
+  a.tiles = a.tiles_x * ((g.ny + 7) / 8);
+  a.zc = div_ddo_chunks(a.tiles, g.nz, cap > 0 && cap < nblk_max ? cap : nblk_max);
+  a.inv2h = 0.5 / h;
+  return a;
 }
 
 // Tiles of tx x (2 ty) columns, z chunks per column; a work item is (tile, z chunk), and the
@@ -886,33 +1120,39 @@ static DArgs div_ddo_shape(const Geom& g, int nblk_max, double h, int cap) {
   a.ty = kRedThreads / a.tx;                 // thread rows; each thread takes two grid rows
   a.tiles_x = (g.nx + a.tx - 1) / a.tx;
   a.tiles = a.tiles_x * ((g.ny + 2 * a.ty - 1) / (2 * a.ty));
-  const int G = cap > 0 && cap < nblk_max ? cap : nblk_max;
-  const int zmax = g.nz >= 16 ? g.nz / 8 : 1;   // at least 8 planes per march where possible
-  double best = -1.0;
-  a.zc = 1;
-  for (int zc = 1; zc <= zmax; ++zc) {
-    const long items = (long)a.tiles * zc;
-    const long grid = items < G ? items : G;
-    const long rounds = (items + grid - 1) / grid;
-    const double eff = ((double)a.tiles * g.nz / G) / ((double)rounds * ((g.nz + zc - 1) / zc));
-    if (eff > best + 1e-9) { best = eff; a.zc = zc; }
-  }
+  a.zc = div_ddo_chunks(a.tiles, g.nz, cap > 0 && cap < nblk_max ? cap : nblk_max);
   a.inv2h = 0.5 / h;
   return a;
 }
 
 int div_ddo_blocks(const Geom& g, int nblk_max, bool fp64) {
   const int cap = fp64 ? div_ddo_cap<double>(g) : div_ddo_cap<float>(g);
-  const DArgs a = div_ddo_shape(g, nblk_max, 1.0, cap);
   const int G = cap > 0 && cap < nblk_max ? cap : nblk_max;
-  const long items = (long)a.tiles * a.zc;
+  long items;
+  if (fp64 ? div_ddo_pairs<double>(g) : div_ddo_pairs<float>(g)) {
+    const DvArgs a = div_ddo2_shape(g, nblk_max, 1.0, cap);
+    items = (long)a.tiles * a.zc;
+  } else {
+    const DArgs a = div_ddo_shape(g, nblk_max, 1.0, cap);
+    items = (long)a.tiles * a.zc;
+  }
   return (int)(items < G ? items : G);
 }
 
 template <typename T>
 hipError_t launch_div_ddo(const T* S, T* div_out, double* partials, int nblk_max, const Geom& g, double h, hipStream_t s) {
-  const DArgs a = div_ddo_shape(g, nblk_max, h, div_ddo_cap<T>(g));
   const dim3 grid(div_ddo_blocks(g, nblk_max, sizeof(T) == 8), g.batch);
+  if constexpr (sizeof(T) == 8) {
+    if (div_ddo_pairs<T>(g)) {
+      const DvArgs a = div_ddo2_shape(g, nblk_max, h, div_ddo_cap<T>(g));
+      if (div_ddo_buf<T>(g))
+        hipLaunchKernelGGL((k_div_ddo2<T, true>), grid, dim3(kRedThreads), 0, s, S, div_out, partials, a);
+      else
+        hipLaunchKernelGGL((k_div_ddo2<T, false>), grid, dim3(kRedThreads), 0, s, S, div_out, partials, a);
+      return hipGetLastError();
+    }
+  }
+  const DArgs a = div_ddo_shape(g, nblk_max, h, div_ddo_cap<T>(g));
   if (div_ddo_buf<T>(g))
     hipLaunchKernelGGL((k_div_ddo<T, true>), grid, dim3(kRedThreads), 0, s, S, div_out, partials, a);
   else

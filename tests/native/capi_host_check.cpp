@@ -172,6 +172,20 @@ void check_status_strings() {
   CHECK(std::strncmp(eq_version(), "libeq", 5) == 0, "version");
 }
 
+void check_ranges_overlap() {
+  // a div_out of three components ending where the six-component field begins does not
+  // overlap it (each range is taken with its own length)
+  alignas(16) static unsigned char buf[4096];
+  const size_t F = 64;                                 // bytes of one component of the batch
+  unsigned char* field = buf + 3 * F;
+  CHECK(!ranges_overlap(buf, 3 * F, field, 6 * F), "adjacent below");
+  CHECK(ranges_overlap(buf + 1, 3 * F, field, 6 * F), "one byte into the field");
+  CHECK(!ranges_overlap(field + 6 * F, 3 * F, field, 6 * F), "adjacent above");
+  CHECK(ranges_overlap(field + 6 * F - 1, 3 * F, field, 6 * F), "last byte of the field");
+  CHECK(ranges_overlap(field + F, 3 * F, field, 6 * F), "inside");
+  CHECK(ranges_overlap(field, 6 * F, field, 6 * F), "same range");
+}
+
 void check_plan_without_device() {
   // null arguments are refused before any device call
   eq_plan_t p = reinterpret_cast<eq_plan_t>(0x1);
@@ -198,6 +212,7 @@ int main() {
   check_symbol_max();
   check_tune_parser();
   check_status_strings();
+  check_ranges_overlap();
   check_plan_without_device();
   std::printf("ok %d\n", g_checks);
   return 0;
