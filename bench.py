@@ -82,6 +82,14 @@ def make_workload(name: str, prec: str):
 TUNE_FILE = os.path.join(ROOT, "profiles", "tune_mi355x.json")
 
 
+def tune_source(args) -> str:
+    if args.no_autotune:
+        return "library defaults"
+    if os.environ.get("EQ_TUNE_SOURCE"):
+        return os.environ["EQ_TUNE_SOURCE"] + " (a configuration it lacks: autotuned in this run)"
+    return os.environ.get("EQ_AUTOTUNE_CACHE") or "autotuned in this run"
+
+
 def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tune=True, removed=True):
     """Time `steps` steps of eq_project (+ eq_residual of the result) on device-resident input.
     removed=False and with_residual=False time the projection alone (no removed part)."""
@@ -102,7 +110,8 @@ def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tu
 
             tuned = autotune(plan, x, out, torch.empty_like(x) if rem is None else rem, reps=3,
                              use_cache=bool(os.environ.get("EQ_AUTOTUNE_CACHE")))
-            log(f"[bench] tuning {prec} {op}: {tuned['tune']} -> {tuned['resolved']}")
+            log(f"[bench] tuning {prec} {op} ({'cached' if tuned.get('from_cache') else 'searched'}): "
+                f"{tuned['tune']} -> {tuned['resolved']}")
         for _ in range(warmup):
             plan.project(x, out, rem)
             if with_residual:
@@ -478,6 +487,18 @@ def main():
     args = ap.parse_args()
     if args.tune_cache:
         os.environ["EQ_AUTOTUNE_CACHE"] = os.path.abspath(args.tune_cache)
+    elif not args.no_autotune and os.path.exists(TUNE_FILE):
+        # the committed tuning, so that bench lines and the committed profiles describe the same
+        # kernel instantiations; read from a private copy, so that a configuration it lacks is
+        # tuned in this run without rewriting the committed file
+        import shutil
+        import tempfile
+
+        fd, copy = tempfile.mkstemp(prefix="eq_tune_", suffix=".json")
+        os.close(fd)
+        shutil.copyfile(TUNE_FILE, copy)
+        os.environ["EQ_AUTOTUNE_CACHE"] = copy
+        os.environ["EQ_TUNE_SOURCE"] = os.path.relpath(TUNE_FILE, ROOT)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: every field runs on a single MI355X "
@@ -552,8 +573,7 @@ def main():
         "hbm_frac_compulsory_48B": (vox / r32["elapsed_s"] * args.steps) * 48 / (HBM_PEAK_GBS * 1e9),
         "residual_of_output": r32["norms"][0] if r32["norms"] else None,
         "tune": r32["tune"],
-        "tune_source": os.environ.get("EQ_AUTOTUNE_CACHE") or ("autotuned in this run" if not args.no_autotune
-                                                                 else "library defaults"),
+        "tune_source": tune_source(args),
         "paper_context": PAPER_CONTEXT,
     }
     if r32["all_stats"]:

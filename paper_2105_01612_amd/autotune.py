@@ -90,7 +90,7 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
     cache = load_cache() if use_cache else {}
     if key in cache:
         plan.tune(**cache[key]["tune"])
-        return cache[key]
+        return dict(cache[key], from_cache=True)
 
     def trial(**kw):
         try:
@@ -182,4 +182,5 @@ def autotune(plan, x, out, rem=None, reps: int = 5, use_cache: bool = True, verb
         cache = load_cache()
         cache[key] = {k: v for k, v in result.items() if k != "search"}
         save_cache(cache)
+    result["from_cache"] = False
     return result
