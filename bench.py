@@ -586,6 +586,10 @@ def main():
         "tune_source": tune_source(args),
         "paper_context": PAPER_CONTEXT,
     }
+    if roof:
+        # beside the slowest kernel's fraction: where the whole step stands against the schedule's
+        # three-round-trip minimum
+        roof["step_frac_of_144B_minimum"] = round(line["hbm_frac_144B_schedule_min"], 4)
     if r32["all_stats"]:
         # algorithmic bytes of every launch of one step, and the rate the whole step sustains
         step_bytes = sum(st["bytes_per_launch"] * st["launches"] for st in r32["all_stats"].values()) / args.steps
@@ -601,6 +605,8 @@ def main():
         line["project_only"] = {"ms": msp, "value": vox / (msp * 1e-3), "unit": "voxels/s",
                                 "hbm_frac_144B_schedule_min": vox / (msp * 1e-3) * 144 / (HBM_PEAK_GBS * 1e9),
                                 "tune": rp["tune"]}
+        if roof:
+            roof["project_only_frac_of_144B_minimum"] = round(line["project_only"]["hbm_frac_144B_schedule_min"], 4)
         del rp
     if args.workload == "batched" and not args.no_cpu_baseline:
         line["error_vs_oracle"] = batched_errors(S32, r32["out"].numpy(), args.op)
