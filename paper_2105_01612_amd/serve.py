@@ -11,8 +11,10 @@ its rank among the sizes, so a small request never waits in a stream behind a la
 one, while requests on different streams overlap on the device.  Completions are
 found by polling events, and every completion frees a slot for the next waiting
 request (no head-of-line blocking across classes).  By default the smallest waiting
-field is admitted first and at most eight requests run at once.  Inputs are taken from device-resident pools, as if produced by
-an upstream GPU stage; the copy into the slot is part of the request's service.
+field is admitted first and at most eight requests run at once.  Inputs are taken from pools,
+device-resident as if produced by an upstream GPU stage, or in pinned host memory (the copy into the
+slot is then the request's transfer over PCIe); the copy into the slot is part of the request's
+service.
 
 The executor is a backend object, so the admission and bookkeeping logic also runs
 on the CPU against a fake backend in the tests.

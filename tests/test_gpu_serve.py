@@ -91,3 +91,27 @@ def test_serving_classes_alone_equal_mix_and_oracle():
         ref, _ = O.project(host[r.n][0].astype(np.float64), "ddo")
         assert frob_rel(mix[r.rid], ref) <= 1e-5, r.n
         del ref
+
+
+def test_pinned_host_pools_equal_device_pools():
+    """Inputs in pinned host memory (each request starts with its transfer over PCIe) give the
+    same bits as device-resident inputs."""
+    import torch
+    from paper_2105_01612_amd.serve import GpuBackend, Request, Server
+
+    sizes = (32, 48)
+    host, pools = _pools(sizes, 2, lambda n: 8)
+    pinned = {n: p.cpu().pin_memory() for n, p in pools.items()}
+    reqs = [Request(i, n, 0.0, i % 2) for i, n in enumerate((32, 48, 32, 48))]
+    got = {}
+    for name, src in (("device", pools), ("pinned", pinned)):
+        be = GpuBackend(src, prec="fp32", op="ddo")
+        srv = Server(be, be.slot_bytes(48) + be.slot_bytes(32))
+        out = {}
+        stats = srv.run(reqs, on_complete=lambda r, o: out.__setitem__(r.rid, o.cpu().numpy().copy()))
+        assert stats["completed"] == len(reqs)
+        srv.close()
+        got[name] = out
+    torch.cuda.synchronize()
+    for r in reqs:
+        assert np.array_equal(got["device"][r.rid], got["pinned"][r.rid]), r
