@@ -74,8 +74,11 @@ enum {
                                FP32 with nx == ny in {64, 128} and nz in {64, 128, 256} (else EQ_ERR_ARG at
                                eq_plan).  Its z stage runs four elements per thread, as the three-pass schedule
                                does with eq_tune zp_e = 4, whose results it equals bit for bit.  A counter wait
-                               that gives up (never expected) is reported by the next eq_residual as
-                               EQ_ERR_DEVICE. */
+                               that gives up (never expected) is reported by eq_residual as
+                               EQ_ERR_DEVICE, then and on every later call: the flag stays set, later
+                               launches of the plan give up early, and the plan must be destroyed.
+                               The environment variable EQ_PERSIST_SPIN_LIMIT (polls, default 262144)
+                               lowers the limit, for tests of this path. */
   EQ_F_OWN_STREAM = 8u      /* the plan creates and owns a non-blocking stream; hip_stream is ignored */
 };
 

@@ -631,7 +631,7 @@ eq_status run_residual(eq_plan_s* p, const void* s, double* norms, void* div_out
     // a persistent launch whose dependency wait gave up (never expected) is reported here
     unsigned gave_up = 0;
     EQ_HIP(hipMemcpy(&gave_up, p->ctr + 2, sizeof(unsigned), hipMemcpyDeviceToHost), "hipMemcpy(counters)");
-    if (gave_up) return fail(EQ_ERR_DEVICE, "a persistent projection's dependency wait gave up; its output is invalid");
+    if (gave_up) return fail(EQ_ERR_DEVICE, "a persistent projection's dependency wait gave up; its output is invalid and the plan must be destroyed");
   }
   const double* host = p->red;
   const double smax2 = p->smax2;

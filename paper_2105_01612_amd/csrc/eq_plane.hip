@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "eq_fft.hpp"
 #include "eq_internal.hpp"
@@ -635,7 +636,13 @@ hipError_t persist_n(const T* in, cplx<T>* W2, T* out, T* removed, const Geom& g
   a.nP = (6 * g.nz + a.gp - 1) / a.gp;
   a.nZ = (zproj_tiles(za) + a.gt - 1) / a.gt;
   a.ctr = ctr;
+  // polls before a wait gives up; EQ_PERSIST_SPIN_LIMIT lowers it so that tests can force the
+  // reported failure while every wait still ends
   a.spin_limit = 1u << 18;
+  if (const char* e = std::getenv("EQ_PERSIST_SPIN_LIMIT")) {
+    const long v = std::atol(e);
+    if (v >= 1 && v < (long)a.spin_limit) a.spin_limit = (unsigned)v;
+  }
   const size_t lds = kPsItemBytes + std::max(PlaneShape<T, N, N, NT, FX, FY>::lds_elems * sizeof(cplx<T>),
                                              zproj_lds(g, sizeof(T) == 8, TC));
   const void* k = reinterpret_cast<const void*>(&k_persist<T, N, NT, FX, FY, FZ>);

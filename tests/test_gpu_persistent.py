@@ -138,3 +138,28 @@ def test_persistent_batch_of_64_every_field_against_oracle(n):
     say("  per-field rel-L2 max", max(errs), "median", float(np.median(errs)))
     assert max(errs) <= 1e-5
     assert max(v[2] for v in norms) <= 2e-6
+
+
+def test_persistent_wait_that_gives_up_is_reported(monkeypatch):
+    """A poll limit of one makes the z and inverse items give up waiting (every wait still ends,
+    the launch completes); eq_residual then reports EQ_ERR_DEVICE for the plan, on every call."""
+    import torch
+    import paper_2105_01612_amd as eq
+
+    monkeypatch.setenv("EQ_PERSIST_SPIN_LIMIT", "1")
+    S = batch((64, 64, 64), 9, 950, grains=8)
+    x = torch.from_numpy(S).cuda()
+    ps = eq.plan(64, batch=9, op="ddo", prec="fp32", flags=["persistent"])
+    out = ps.project(x)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        with pytest.raises(eq.EqError) as ei:
+            ps.residual(out)
+        assert ei.value.code == "EQ_ERR_DEVICE"
+    ps.destroy()
+    monkeypatch.delenv("EQ_PERSIST_SPIN_LIMIT")
+    # a new plan is unaffected
+    ok = eq.plan(64, batch=9, op="ddo", prec="fp32", flags=["persistent"])
+    ok.project(x, out)
+    ok.residual(out)
+    ok.destroy()
