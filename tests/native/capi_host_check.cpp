@@ -138,20 +138,21 @@ void check_symbol_max() {
 }
 
 void check_tune_parser() {
-  const struct { const char* env; int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4, xsplit; } cases[] = {
-      {"tx_y=16,tx_z=32,rw_x=4,chunk=32,radix16=2,schedule=5", 16, 32, 4, 32, 2, 5, 0, 0, 0},
-      {"schedule=3 tc_zp=8", 0, 0, 0, 0, -1, 3, 8, 0, 0},
-      {"zp_e=4,schedule=3", 0, 0, 0, 0, -1, 3, 0, 0, 0},
-      {"radix4=1,xsplit=2,,", 0, 0, 0, 0, -1, 0, 0, 1, 2},
-      {"", 0, 0, 0, 0, -1, 0, 0, 0, 0},
-      {",,,=,=5,tx_y=,unknown=3,tx_z", 0, 0, 0, 0, -1, 0, 0, 0, 0},
-      {"tx_y=abc,rw_x=-3", 0, 0, -3, 0, -1, 0, 0, 0, 0},
+  const struct { const char* env; int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4, xsplit, zp_e; } cases[] = {
+      {"tx_y=16,tx_z=32,rw_x=4,chunk=32,radix16=2,schedule=5", 16, 32, 4, 32, 2, 5, 0, 0, 0, 0},
+      {"schedule=3 tc_zp=8", 0, 0, 0, 0, -1, 3, 8, 0, 0, 0},
+      {"zp_e=4,schedule=3", 0, 0, 0, 0, -1, 3, 0, 0, 0, 4},
+      {"radix4=1,xsplit=2,,", 0, 0, 0, 0, -1, 0, 0, 1, 2, 0},
+      {"", 0, 0, 0, 0, -1, 0, 0, 0, 0, 0},
+      {",,,=,=5,tx_y=,unknown=3,tx_z", 0, 0, 0, 0, -1, 0, 0, 0, 0, 0},
+      {"tx_y=abc,rw_x=-3", 0, 0, -3, 0, -1, 0, 0, 0, 0, 0},
   };
   for (const auto& c : cases) {
     setenv("EQ_TUNE", c.env, 1);
     const Tune t = tune_from_env();
     CHECK(t.tx_y == c.tx_y && t.tx_z == c.tx_z && t.rw_x == c.rw_x && t.chunk == c.chunk && t.radix16 == c.radix16 &&
-              t.schedule == c.schedule && t.tc_zp == c.tc_zp && t.radix4 == c.radix4 && t.xsplit == c.xsplit,
+              t.schedule == c.schedule && t.tc_zp == c.tc_zp && t.radix4 == c.radix4 && t.xsplit == c.xsplit &&
+              t.zp_e == c.zp_e,
           "EQ_TUNE=\"%s\"", c.env);
   }
   std::string longv;
