@@ -202,8 +202,10 @@ eq_status eq_plan_reset_stats(eq_plan_t p);
  *            nx == ny in {64, 128, 256} (FP64: 64, 128) and nz in {64, 128, 256};
  *            0 = library default (three passes where available and nx <= 128),
  *   tc_zp    (ky, kx) columns per workgroup of the three-pass z projection (must divide ny),
- *   radix4   1: radix-4 stages on x (FP32, nx a power of two in 32 .. 512: the six-component
- *            x kernel then holds 6 x 4 values per lane instead of 6 x 8); ignored elsewhere,
+ *   radix4   1: radix-4 stages on x (FP32): nx a power of two in 32 .. 512 (the six-component
+ *            x kernel then holds 6 x 4 values per lane instead of 6 x 8), or nx 96, 160, 192,
+ *            320 or 384 with the split x kernel (xsplit 0 or 2; E = 12 or 20 instead of 24 or
+ *            40); ignored elsewhere and with xsplit = 1 on those edges,
  *   xsplit   x pass kernel: 2 = six components split over the two halves of a wavefront
  *            (three rows of E values per lane; needs nx / E to divide 32), 1 = not split,
  *            0 = library default; reported as 1 or 2,

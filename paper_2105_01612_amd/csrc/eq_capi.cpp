@@ -61,14 +61,17 @@ bool factor_axis(int n, AxisFft* out, bool wide = false, bool narrow = false) {
   FftDesc d{};
   d.n = n;
   int k = 0;
-  if (narrow && b == 0 && c == 0 && a >= 3) {
-    // radix-4 stages (E = 4): a quarter of the registers per lane of radix 16
+  if (narrow && a >= 3 && !(b > 0 && c > 0)) {
+    // radix-4 stages (E = 4; with a factor 3 or 5, E = 12 or 20): a third to a half of the
+    // registers per lane of the radix-8 schedules
     for (int i = 0; i < a / 2; ++i) d.r[k++] = 4;
     if (a % 2) d.r[k++] = 2;
+    for (int i = 0; i < b; ++i) d.r[k++] = 3;
+    for (int i = 0; i < c; ++i) d.r[k++] = 5;
     if (k > kMaxStages) return false;
     d.nst = k;
     out->d = d;
-    out->E = 4;
+    out->E = b > 0 ? 12 : (c > 0 ? 20 : 4);
     out->fast = true;
     return true;
   }
@@ -380,6 +383,9 @@ eq_status check_shapes(const eq_plan_s* p, const Tune& tn) {
   if (tz < 2 || (tz & 1) || g.nx % tz || round64(thz) > max_threads(p->az))
     return fail(EQ_ERR_ARG, "tx_z does not fit this grid");
   if (rw < 1 || round64(thx) > max_threads(p->ax)) return fail(EQ_ERR_ARG, "rw_x does not fit this grid");
+  // the radix-4 schedules of 3/5-smooth edges (E = 12, 20) exist for the split x kernel only
+  if (p->ax.fast && (p->ax.E == 12 || p->ax.E == 20) && !x_split(p->ax, eb, tn))
+    return fail(EQ_ERR_ARG, "radix4 on a 3/5-smooth x edge needs the split x kernel (xsplit 0 or 2)");
   if (tn.chunk < -1 || tn.chunk > g.batch * g.nzh) return fail(EQ_ERR_ARG, "chunk out of range");
   if (tn.schedule != 0 && tn.schedule != 3 && tn.schedule != 5) return fail(EQ_ERR_ARG, "schedule must be 0, 3 or 5");
   const bool fp64 = p->desc.prec == EQ_FP64;
@@ -432,10 +438,12 @@ Tune tune_from_env() {
 // Radix schedules of the three axes for a radix-16 mask (-1: y only); radix4 = 1 puts the x
 // axis on radix-4 stages where the six-component x kernel serves it (FP32, powers of two
 // 32 .. 512), and is ignored elsewhere.
-void set_axes(eq_plan_s* p, int mask, int radix4 = 0) {
+void set_axes(eq_plan_s* p, int mask, int radix4 = 0, int xsplit = 0) {
   if (mask < 0) mask = 2;
   const int nx = p->desc.nx;
-  const bool x4 = radix4 == 1 && x6_radix4_available(nx, p->desc.prec == EQ_FP64);
+  // radix 4 on a 3/5-smooth x axis has only the split kernel's schedules (E = 12 or 20)
+  const bool pow2 = (nx & (nx - 1)) == 0;
+  const bool x4 = radix4 == 1 && (pow2 || xsplit != 1) && x6_radix4_available(nx, p->desc.prec == EQ_FP64);
   factor_axis(nx, &p->ax, (mask & 1) != 0, x4);
   // the one-line-per-thread-group x pass needs 6 * nx / E threads in one workgroup: past 512
   // (nx = 1024 on radix 8) take radix 16
@@ -711,7 +719,7 @@ eq_status eq_plan(const eq_desc* d, void* hip_stream, eq_plan_t* out) {
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }
   p->tune = tune_from_env();
-  set_axes(p, p->tune.radix16, p->tune.radix4);
+  set_axes(p, p->tune.radix16, p->tune.radix4, p->tune.xsplit);
   if ((st = check_shapes(p, p->tune)) != EQ_OK) { release(p); return st; }
   if (d->flags & EQ_F_OWN_STREAM) {
     e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
@@ -918,7 +926,7 @@ eq_status eq_plan_tune(eq_plan_t p, const eq_tune* tv) {
   t.zp_e = tv->zp_e;
   DeviceGuard dg(p->device);
   const AxisFft ax = p->ax, ay = p->ay, az = p->az;
-  set_axes(p, t.radix16, t.radix4);
+  set_axes(p, t.radix16, t.radix4, t.xsplit);
   eq_status st = check_shapes(p, t);
   if (st != EQ_OK) {
     p->ax = ax; p->ay = ay; p->az = az;
@@ -938,7 +946,7 @@ eq_status eq_plan_get_tune(eq_plan_t p, eq_tune* t) {
   t->rw_x = pick_rw_x(p->g, p->ax, eb, p->tune);
   t->chunk = chunk_planes(p);
   t->radix16 = (p->ax.E == 16 ? 1 : 0) | (p->ay.E == 16 ? 2 : 0) | (p->az.E == 16 ? 4 : 0);
-  t->radix4 = p->ax.E == 4 ? 1 : 0;
+  t->radix4 = (p->ax.E == 4 || p->ax.E == 12 || p->ax.E == 20) ? 1 : 0;
   t->xsplit = x_split(p->ax, eb, p->tune) ? 2 : 1;
   const bool plane = use_plane(p, p->tune);
   t->schedule = plane ? 3 : 5;

@@ -750,7 +750,9 @@ bool ct_enabled() {
 template <typename T>
 void dispatch_fast(const FastArgs<T>& a) {
   if (ct_enabled() && (ct_launch_pow2<T>(a) || ct_launch_mixed<T>(a))) return;
-  if (a.E == 4) return;   // unreachable: radix-4 plans exist only where the x6 schedules above serve them
+  // unreachable: radix-4 plans (E = 4, 12, 20) exist only where the x6 schedules above serve
+  // them (the planner checks), and no run-time engine has these E
+  if (a.E == 4 || a.E == 12 || a.E == 20) return;
   switch (a.E) {
     case 8: launch_with<T, RtFft<8>>(a); break;
     case 16: launch_with<T, RtFft<16>>(a); break;
@@ -799,18 +801,35 @@ bool x6s_schedule(const AxisFft& ax) {
   return ct_launch_pow2<T>(f) || ct_launch_mixed<T>(f);
 }
 bool x_split(const AxisFft& ax, int eb, const Tune& tn) {
-  if (tn.xsplit == 1 || (tn.xsplit == 0 && ax.E > 16)) return false;
+  // E = 12 and 20 (radix 4 with a factor 3 or 5) exist only for the split kernel, so it is their default
+  if (tn.xsplit == 1 || (tn.xsplit == 0 && ax.E > 16 && ax.E != 20)) return false;
   if (!ax.fast || !ct_enabled() || ax.E % 2 != 0) return false;
   const int P = ax.d.n / ax.E;
   if (P < 1 || (P > 32 && P != 64) || (P <= 32 && 32 % P != 0)) return false;
   return eb == 8 ? x6s_schedule<float>(ax) : x6s_schedule<double>(ax);
 }
 bool x6_radix4_available(int nx, bool fp64) {
+  if (fp64) return false;
   AxisFft ax{};
   ax.d.n = nx;
   ax.E = 4;
   ax.fast = true;
-  return !fp64 && use_x6<float>(ax);
+  if (use_x6<float>(ax)) return true;          // powers of two: the six-component kernels, E = 4
+  // 3- or 5-smooth: the split kernel on a radix-4 schedule (E = 12 or 20), where one exists
+  int m = nx, a = 0, b = 0, c = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  while (m % 3 == 0) { m /= 3; ++b; }
+  while (m % 5 == 0) { m /= 5; ++c; }
+  if (m != 1 || a < 3 || (b > 0) == (c > 0)) return false;
+  ax.E = b > 0 ? 12 : 20;
+  int k = 0;
+  for (int i = 0; i < a / 2; ++i) ax.d.r[k++] = 4;
+  if (a % 2) ax.d.r[k++] = 2;
+  for (int i = 0; i < b; ++i) ax.d.r[k++] = 3;
+  for (int i = 0; i < c; ++i) ax.d.r[k++] = 5;
+  ax.d.nst = k;
+  const int P = nx / ax.E;
+  return ct_enabled() && P >= 1 && P <= 32 && 32 % P == 0 && x6s_schedule<float>(ax);
 }
 // Register-engine shapes aim at ~256 threads per workgroup (several workgroups per
 // CU so load, transform and store phases of different workgroups overlap) with

@@ -110,6 +110,8 @@ int main(int argc, char** argv) {
     case 16: sweep<double, 16>(d, "f64"); sweep<float, 16>(d, "f32"); break;
     case 24: sweep<double, 24>(d, "f64"); sweep<float, 24>(d, "f32"); break;
     case 40: sweep<double, 40>(d, "f64"); sweep<float, 40>(d, "f32"); break;
+    case 12: sweep<double, 12>(d, "f64"); sweep<float, 12>(d, "f32"); break;
+    case 20: sweep<double, 20>(d, "f64"); sweep<float, 20>(d, "f32"); break;
     default: return 2;
   }
   return 0;

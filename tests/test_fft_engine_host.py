@@ -20,6 +20,7 @@ SCHEDULES = [
     (8, [8]), (8, [8, 2]), (8, [8, 4]), (8, [8, 8]), (16, [16, 8]), (16, [16, 16]), (16, [16, 8, 4]),
     (16, [16, 16, 4]), (24, [8, 3]), (24, [8, 2, 3]), (24, [8, 4, 3]), (24, [8, 8, 3]), (24, [8, 8, 2, 3]),
     (24, [8, 3, 3]), (40, [8, 5]), (40, [8, 4, 5]), (40, [8, 8, 5]), (40, [8, 5, 5, 5]),
+    (12, [4, 4, 2, 3]), (12, [4, 4, 4, 3]), (12, [4, 4, 4, 2, 3]), (20, [4, 4, 2, 5]), (20, [4, 4, 4, 5]),
 ]
 
 

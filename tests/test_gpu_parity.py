@@ -232,11 +232,37 @@ def test_radix4_x_parity(op, shape):
     plan.destroy()
 
 
+@pytest.mark.parametrize("nx", [96, 160, 192, 384])
+def test_radix4_on_3_5_smooth_x_takes_the_split_kernel(nx):
+    """radix4 = 1 on a 3- or 5-smooth x edge (E = 12 or 20) with the x kernel left to the
+    library: the split kernel serves it and the projection matches the oracle.  With the
+    unsplit kernel asked for, radix4 is ignored there (no unsplit kernel has these schedules):
+    the radix-8 line kernel runs, and the projection still matches."""
+    eq = eqmod()
+    shape = (4, 6, nx)
+    S = wl.voronoi_field(wl.FieldSpec(shape, grains=5, sigma_grain=80.0, sigma_noise=4.0, seed=nx + 1))
+    ref, _ = O.project(upcast(S, "fp32"), "ddo")
+    plan = eq.plan(nx, 6, 4, op="ddo", prec="fp32")
+    plan.tune(schedule=5, radix4=1)
+    t = plan.get_tune()
+    assert t["radix4"] == 1 and t["xsplit"] == 2, t
+    got = plan.project(to_dev(S, "fp32")).double().cpu().numpy()
+    assert rel_l2(got, ref) <= TOL["fp32"]
+    plan.tune(schedule=5, radix4=1, xsplit=1)
+    t = plan.get_tune()
+    assert t["radix4"] == 0 and t["xsplit"] == 1, t
+    got = plan.project(to_dev(S, "fp32")).double().cpu().numpy()
+    assert rel_l2(got, ref) <= TOL["fp32"]
+    plan.destroy()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("op", ["cdo", "ddo"])
 @pytest.mark.parametrize("shape,radix,P", [((16, 12, 32), {}, 4), ((20, 6, 64), {}, 8), ((8, 10, 128), {}, 16),
                                            ((4, 10, 256), {}, 32), ((6, 18, 96), {}, 4), ((6, 10, 160), {}, 4),
                                            ((4, 6, 192), {}, 8), ((6, 10, 128), {"radix4": 1}, 32),
+                                           ((6, 18, 96), {"radix4": 1}, 8), ((6, 10, 160), {"radix4": 1}, 8),
+                                           ((4, 6, 192), {"radix4": 1}, 16), ((4, 6, 384), {"radix4": 1}, 32),
                                            ((4, 6, 256), {"radix16": 1}, 16), ((4, 6, 512), {}, 64)])
 def test_xsplit_parity(prec, op, shape, radix, P):
     """The x pass split over wavefront halves (three rows per lane, frequencies divided
