@@ -82,12 +82,18 @@ def make_workload(name: str, prec: str):
 TUNE_FILE = os.path.join(ROOT, "profiles", "tune_mi355x.json")
 
 
+SEARCHED = []   # (prec, op, grid) of the plans whose tuning was searched in this run, not read
+
+
 def tune_source(args) -> str:
     if args.no_autotune:
         return "library defaults"
-    if os.environ.get("EQ_TUNE_SOURCE"):
-        return os.environ["EQ_TUNE_SOURCE"] + " (a configuration it lacks: autotuned in this run)"
-    return os.environ.get("EQ_AUTOTUNE_CACHE") or "autotuned in this run"
+    src = os.environ.get("EQ_TUNE_SOURCE") or os.environ.get("EQ_AUTOTUNE_CACHE")
+    if not src:
+        return "autotuned in this run"
+    if not SEARCHED:
+        return f"{src} (every plan of this run)"
+    return f"{src}; searched in this run, absent from it: " + ", ".join(f"{p} {o} {g}" for p, o, g in SEARCHED)
 
 
 def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tune=True, removed=True):
@@ -110,6 +116,8 @@ def run_gpu(S_host, op, prec, steps, warmup, with_residual=True, timing=True, tu
 
             tuned = autotune(plan, x, out, torch.empty_like(x) if rem is None else rem, reps=3,
                              use_cache=bool(os.environ.get("EQ_AUTOTUNE_CACHE")))
+            if not tuned.get("from_cache"):
+                SEARCHED.append((prec, op, "x".join(map(str, (nx, ny, nz))) + (f" x{B}" if B > 1 else "")))
             log(f"[bench] tuning {prec} {op} ({'cached' if tuned.get('from_cache') else 'searched'}): "
                 f"{tuned['tune']} -> {tuned['resolved']}")
         for _ in range(warmup):

@@ -88,3 +88,19 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_tune_source_names_the_plans_searched_in_the_run(monkeypatch):
+    class A:
+        no_autotune = False
+    monkeypatch.setattr(bench, "SEARCHED", [])
+    monkeypatch.delenv("EQ_AUTOTUNE_CACHE", raising=False)
+    monkeypatch.delenv("EQ_TUNE_SOURCE", raising=False)
+    assert bench.tune_source(A) == "autotuned in this run"
+    monkeypatch.setenv("EQ_AUTOTUNE_CACHE", "/tmp/copy.json")
+    monkeypatch.setenv("EQ_TUNE_SOURCE", "profiles/tune_mi355x.json")
+    assert bench.tune_source(A) == "profiles/tune_mi355x.json (every plan of this run)"
+    bench.SEARCHED.append(("fp32", "ddo", "96x96x96"))
+    assert bench.tune_source(A).endswith("absent from it: fp32 ddo 96x96x96")
+    A.no_autotune = True
+    assert bench.tune_source(A) == "library defaults"
