@@ -157,11 +157,11 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* __restrict__ in, cplx
                                         threadIdx.x);
 }
 
-// Inverse plane `plane` of `planes`.
+// Inverse plane `plane` of `planes`.  out may be in (in place): each thread reads the input
+// values it overwrites, and no others, so out, in and removed carry no __restrict__.
 template <typename T, int NX, int NY, int NT, typename FX, typename FY>
-__device__ __forceinline__ void plane_c2r_body(const cplx<T>* __restrict__ W2, T* __restrict__ out,
-                                               const T* __restrict__ in, T* __restrict__ removed, int plane,
-                                               int planes, const cplx<T>* __restrict__ twx,
+__device__ __forceinline__ void plane_c2r_body(const cplx<T>* __restrict__ W2, T* out, const T* in, T* removed,
+                                               int plane, int planes, const cplx<T>* __restrict__ twx,
                                                const cplx<T>* __restrict__ twy, T scale, cplx<T>* lds, int tid) {
   using C = cplx<T>;
   using S = PlaneShape<T, NX, NY, NT, FX, FY>;
@@ -255,8 +255,7 @@ __device__ __forceinline__ void plane_c2r_body(const cplx<T>* __restrict__ W2, T
 }
 
 template <typename T, int NX, int NY, int NT, typename FX, typename FY>
-__global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2, T* __restrict__ out,
-                                                  const T* __restrict__ in, T* __restrict__ removed,
+__global__ __launch_bounds__(NT) void k_plane_c2r(const cplx<T>* __restrict__ W2, T* out, const T* in, T* removed,
                                                   const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
                                                   T scale) {
   extern __shared__ unsigned char smem_raw[];
@@ -386,8 +385,8 @@ __global__ __launch_bounds__(kMaxFastThreads) void k_zproj(cplx<T>* __restrict__
 constexpr size_t kPsItemBytes = 16;   // LDS ahead of the bodies' LDS in the persistent launch
 
 template <typename T, int N, int NT, typename FX, typename FY, typename FZ>
-__global__ __launch_bounds__(NT) void k_persist(const T* __restrict__ in, cplx<T>* __restrict__ W2, T* __restrict__ out,
-                                               T* __restrict__ removed, PsArgs a, ZpArgs za,
+__global__ __launch_bounds__(NT) void k_persist(const T* in, cplx<T>* __restrict__ W2, T* out, T* removed, PsArgs a,
+                                               ZpArgs za,
                                                const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
                                                const cplx<T>* __restrict__ twz, const double* __restrict__ symu,
                                                T scale) {

@@ -356,6 +356,43 @@ def test_in_place_and_determinism():
     plan.destroy()
 
 
+@pytest.mark.parametrize("route", [
+    # (prec, grid, batch, schedule asked for, flags, schedule taken)
+    ("fp32", (96, 96, 96), 1, None, (), 5),                    # five passes (3/5-smooth edge)
+    ("fp32", (64, 64, 64), 2, 5, (), 5),                       # five passes on a three-pass grid
+    ("fp32", (64, 64, 64), 2, 3, (), 3),                       # three passes
+    ("fp64", (64, 64, 64), 2, 3, (), 3),
+    ("fp32", (128, 128, 128), 1, 3, (), 3),
+    ("fp32", (64, 64, 64), 9, None, ("persistent",), 3),       # one launch, items of four planes
+    ("fp32", (128, 128, 128), 2, None, ("persistent",), 3),
+])
+def test_in_place_on_every_route(route):
+    """s_eq == s_in gives the bits of the out-of-place call, with and without the removed part:
+    the last pass reads each input value it overwrites before writing it."""
+    eq = eqmod()
+    torch = torch_mod()
+    prec, (nz, ny, nx), b, schedule, flags, taken = route
+    say("in place", route)
+    S = np.stack([wl.voronoi_field(wl.FieldSpec((nz, ny, nx), grains=12, sigma_grain=80.0, sigma_noise=6.0,
+                                                seed=70 + f)) for f in range(b)])
+    x = to_dev(S, prec)
+    plan = eq.plan(nx, ny, nz, batch=b, op="ddo", prec=prec, flags=list(flags))
+    if schedule is not None:
+        plan.tune(schedule=schedule)
+    assert plan.get_tune()["schedule"] == taken
+    ref, ref_rem = torch.empty_like(x), torch.empty_like(x)
+    plan.project(x, ref, ref_rem)
+    for with_removed in (True, False):
+        y = x.clone()
+        rem = torch.full_like(x, float("nan")) if with_removed else None
+        plan.project(y, y, rem)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), with_removed
+        if with_removed:
+            assert torch.equal(rem, ref_rem)
+    plan.destroy()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_invariants_on_gpu_output(prec):
     eq = eqmod()
