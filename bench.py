@@ -304,7 +304,19 @@ def run_serve(args):
         del arr
     torch.cuda.synchronize()
     log(f"[bench] serve pools generated in {time.perf_counter() - t:.1f}s: {pool_n}")
-    be = GpuBackend(pools, prec="fp32", op=args.op)
+    # each class's plans take the tune file's entry for their configuration (no search while serving)
+    cache = None if args.no_autotune else os.environ.get("EQ_AUTOTUNE_CACHE")
+    tuned_classes = []
+    if cache:
+        import types
+
+        from paper_2105_01612_amd.autotune import cache_key, load_cache
+
+        entries = load_cache(cache)
+        tuned_classes = [n for n in sizes if cache_key(types.SimpleNamespace(nx=n, ny=n, nz=n, batch=1, prec="fp32",
+                                                                             op=args.op)) in entries]
+        cache_name = os.environ.get("EQ_TUNE_SOURCE") or cache
+    be = GpuBackend(pools, prec="fp32", op=args.op, tune_cache=cache)
     srv = Server(be, int(args.budget_gb * 2 ** 30))          # smallest first, at most 8 in flight
     srv.warm(sizes)
     ns = wl.request_sizes(args.requests, seed=4000, sizes=sizes)
@@ -336,7 +348,7 @@ def run_serve(args):
     del pools
     torch.cuda.empty_cache()
     m = min(args.requests, 500)
-    be_h = GpuBackend(host_pools, prec="fp32", op=args.op)
+    be_h = GpuBackend(host_pools, prec="fp32", op=args.op, tune_cache=cache)
     srv_h = Server(be_h, int(args.budget_gb * 2 ** 30))
     srv_h.warm(sizes)
     sat_h = srv_h.run([Request(i, int(n), 0.0, f) for i, (n, f) in enumerate(zip(ns[:m], fields[:m]))])
@@ -355,6 +367,7 @@ def run_serve(args):
             "arrival_rate_per_s": lam, "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
             "p99_ms_by_size": {k: v["p99_ms"] for k, v in res["per_size"].items()},
             "policy": "smallest first, 8 in flight, 4 streams by size class",
+            "tune_source": f"{cache_name} (classes with an entry: {tuned_classes})" if cache else "library defaults",
             "saturated": sat, "at_0.7_saturation": res, "at_1.2_saturation": over,
             "policies_at_0.7_saturation": policies, "h2d_inclusive": h2d}
 
@@ -429,12 +442,20 @@ def run_inloop(args):
                 plan = eq.plan(n, op=args.op, prec="fp32", flags=flags, stream=stream)
                 a = torch.from_numpy(x0).cuda()
                 b = torch.empty_like(a)
+                tune = None
+                if not persistent and not args.no_autotune:
+                    from paper_2105_01612_amd.autotune import autotune
+
+                    tuned = autotune(plan, a, b, None, reps=3, use_cache=bool(os.environ.get("EQ_AUTOTUNE_CACHE")))
+                    if not tuned.get("from_cache"):
+                        SEARCHED.append(("fp32", args.op, f"{n}x{n}x{n}"))
+                    tune = tuned["resolved"]
                 plan.project(a, b)
                 first = b.cpu().numpy()
                 dt, lat = _inloop_rate(plan, a, b, stream, 200 if n < 256 else 60)
                 plan.destroy()
                 final = b.cpu().numpy()
-            row = {"n": n, "persistent": persistent, "replays": (200 if n < 256 else 60) + 50,
+            row = {"n": n, "persistent": persistent, "tune": tune, "replays": (200 if n < 256 else 60) + 50,
                    "projections_per_s": 1.0 / dt, "voxels_per_s": n ** 3 / dt,
                    "p50_ms": statistics.median(lat), "p99_ms": float(np.percentile(lat, 99))}
             if n < 256:
@@ -458,7 +479,7 @@ def run_inloop(args):
     return {"metric": "repeated in-loop projections (graph replay, one plan)", "value": head["projections_per_s"],
             "unit": "projections/s (128^3 FP32)", "higher_is_better": True, "n_gpus": 1,
             "data": "synthetic: serving pool field 0 per size", "config": {"workload": "inloop", "op": args.op},
-            "error_vs_oracle_tol": 1e-5,
+            "error_vs_oracle_tol": 1e-5, "tune_source": tune_source(args),
             "results": rows}
 
 

@@ -48,12 +48,23 @@ def cache_key(plan, arch: Optional[str] = None) -> str:
     return f"{arch}|{plan.nx}x{plan.ny}x{plan.nz}|b{plan.batch}|{plan.prec}|{plan.op}"
 
 
-def load_cache() -> Dict[str, dict]:
+def load_cache(path: Optional[str] = None) -> Dict[str, dict]:
     try:
-        with open(cache_path()) as fh:
+        with open(path or cache_path()) as fh:
             return json.load(fh)
     except (OSError, ValueError):
         return {}
+
+
+def apply_cached(plan, path: Optional[str] = None) -> Optional[dict]:
+    """Apply the cached tuning of the plan's configuration (the file at `path`, else the default
+    cache) and return it; without an entry, return None and leave the plan's defaults.  Never
+    searches, so it is cheap enough for plans made while requests are being served."""
+    entry = load_cache(path).get(cache_key(plan))
+    if not entry:
+        return None
+    plan.tune(**entry["tune"])
+    return entry["tune"]
 
 
 def save_cache(cache: Dict[str, dict]) -> None:

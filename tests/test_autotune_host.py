@@ -56,3 +56,25 @@ def test_cached_entry_is_applied_without_trials(tmp_path, monkeypatch):
     got = at.autotune(plan, None, None, use_cache=True)
     assert got["tune"] == {"tx_y": 16, "schedule": 3}
     assert calls == [("tune", {"tx_y": 16, "schedule": 3})]
+
+
+def test_apply_cached_reads_the_named_file_and_never_searches(tmp_path, monkeypatch):
+    """apply_cached (serving slots): the entry of the plan's configuration in the named file is
+    applied; a configuration without one keeps its defaults, and nothing is timed or written."""
+    monkeypatch.setenv(at.CACHE_ENV, str(tmp_path / "default.json"))      # not the file named below
+    monkeypatch.setattr(at, "_arch", lambda: "gfx950")
+    path = tmp_path / "classes.json"
+    path.write_text(json.dumps({"gfx950|128x128x128|b1|fp32|ddo": {"tune": {"tc_zp": 8, "zp_e": 4}}}))
+    calls = []
+
+    def mk(n):
+        p = fake_plan(n, n, n)
+        p.tune = lambda **kw: calls.append((n, kw))
+        p.project = lambda *a, **k: calls.append((n, "project"))
+        return p
+
+    assert at.apply_cached(mk(128), str(path)) == {"tc_zp": 8, "zp_e": 4}
+    assert at.apply_cached(mk(64), str(path)) is None
+    assert at.apply_cached(mk(128), str(tmp_path / "absent.json")) is None
+    assert calls == [(128, {"tc_zp": 8, "zp_e": 4})]
+    assert not (tmp_path / "default.json").exists()
