@@ -69,13 +69,14 @@ class GpuBackend:
     `streams` streams by size class (see stream_of_size)."""
 
     def __init__(self, pools: Dict[int, "object"], prec: str = "fp32", op: str = "ddo", h: float = 1.0,
-                 streams: int = 4, tune_cache: Optional[str] = None):
+                 streams: int = 4, tune_cache: Optional[str] = None, graphs: bool = True):
         import torch
 
         import paper_2105_01612_amd as eq
 
         self.torch, self.eq = torch, eq
         self.tune_cache = tune_cache  # autotune results file: a slot's plan takes its class's entry
+        self.graphs = graphs          # replay a captured hipGraph per slot, else launch the passes
         self.pools = pools            # n -> device tensor (k, 6, n, n, n)
         self.prec, self.op, self.h = prec, op, h
         self.dtype = torch.float32 if prec == "fp32" else torch.float64
@@ -89,7 +90,8 @@ class GpuBackend:
     def create(self, n: int):
         torch = self.torch
         stream = self.streams[stream_of_size(n, self.sizes, len(self.streams))]
-        plan = self.eq.plan(n, op=self.op, prec=self.prec, h=self.h, flags=["capture_graph"], stream=stream)
+        plan = self.eq.plan(n, op=self.op, prec=self.prec, h=self.h, flags=["capture_graph"] if self.graphs else [],
+                            stream=stream)
         if self.tune_cache:
             from .autotune import apply_cached
 

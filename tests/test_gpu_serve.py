@@ -115,3 +115,41 @@ def test_pinned_host_pools_equal_device_pools():
     torch.cuda.synchronize()
     for r in reqs:
         assert np.array_equal(got["device"][r.rid], got["pinned"][r.rid]), r
+
+
+def test_tuned_slots_without_graphs_give_the_graph_bits(tmp_path):
+    """Slots that launch their passes (graphs=False) return the bits of graph-replaying slots. A slot
+    whose plan takes a tune-file entry runs that entry: bitwise the same for a class without one,
+    within the oracle bar for the class whose entry changes the z stage's radices."""
+    import json
+    import types
+
+    import torch
+    from paper_2105_01612_amd.autotune import cache_key
+    from paper_2105_01612_amd.serve import GpuBackend, Request, Server
+
+    sizes = (64, 96)
+    host, pools = _pools(sizes, 2, lambda n: max(2, n ** 3 // 16 ** 3))
+    # an entry for 64^3 that changes the z stage's shape (four elements per thread, eight columns)
+    path = tmp_path / "tune.json"
+    key = cache_key(types.SimpleNamespace(nx=64, ny=64, nz=64, batch=1, prec="fp32", op="ddo"))
+    path.write_text(json.dumps({key: {"tune": {"schedule": 3, "zp_e": 4, "tc_zp": 8}}}))
+    reqs = [Request(i, n, 0.0, i % 2) for i, n in enumerate((64, 96, 64, 96))]
+    got = {}
+    for name, kw in (("graph", {}), ("stream", {"graphs": False}), ("tuned", {"graphs": False, "tune_cache": str(path)})):
+        be = GpuBackend(pools, prec="fp32", op="ddo", **kw)
+        srv = Server(be, 4 * be.slot_bytes(96))
+        out = {}
+        srv.run(list(Request(r.rid, r.n, 0.0, r.field) for r in reqs),
+                on_complete=lambda q, o: out.__setitem__(q.rid, o.cpu().numpy().copy()))
+        srv.close()
+        got[name] = out
+        torch.cuda.synchronize()
+    for r in reqs:
+        assert np.array_equal(got["stream"][r.rid], got["graph"][r.rid]), r
+        if r.n == 96:
+            assert np.array_equal(got["tuned"][r.rid], got["graph"][r.rid]), r
+        else:
+            # the z stage's element count changes the transform's rounding order: same bar as the oracle
+            ref, _ = O.project(host[64][r.field].astype(np.float64), "ddo")
+            assert frob_rel(got["tuned"][r.rid], ref) <= 1e-5
