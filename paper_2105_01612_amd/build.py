@@ -84,5 +84,26 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     return LIB
 
 
+CONSUMER_SRC = os.path.join(ROOT, "tests", "native", "capi_gpu_consumer.cpp")
+CONSUMER = os.path.join(ROOT, "tests", "native", "bin", "capi_gpu_consumer")
+
+
+def build_consumer(verbose: bool = False) -> str:
+    """Build the test program that calls libeq through include/eq.h only (no Python), linked
+    against the libeq.so next to this file (found at run time through a relative rpath)."""
+    os.makedirs(os.path.dirname(CONSUMER), exist_ok=True)
+    rpath = "-Wl,-rpath,$ORIGIN/" + os.path.relpath(HERE, os.path.dirname(CONSUMER))
+    cmd = ([hipcc()] + common_flags() + ["-x", "hip", CONSUMER_SRC, "-x", "none", "-L", HERE, "-leq", rpath,
+                                         "-o", CONSUMER + ".tmp"])
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {CONSUMER_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(CONSUMER + ".tmp", CONSUMER)
+    return CONSUMER
+
+
 if __name__ == "__main__":
     print(build(verbose=True, incremental="--incremental" in sys.argv[1:]))
+    print(build_consumer(verbose=True))
