@@ -60,12 +60,14 @@ def to_dev(a, prec):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
 
 
-def run_project(S, op, prec, h=1.0, removed=True, flags=0, schedule=None):
+def run_project(S, op, prec, h=1.0, removed=True, flags=0, schedule=None, tuning=None):
     eq = eqmod()
     torch = torch_mod()
     batch = S.shape[0] if S.ndim == 5 else 1
     nz, ny, nx = S.shape[-3:]
     plan = eq.plan(nx, ny, nz, batch=batch, op=op, prec=prec, h=h, flags=flags)
+    if tuning is not None:
+        tuning(plan)
     if schedule is not None:
         plan.tune(schedule=schedule)
         assert plan.get_tune()["schedule"] == schedule
@@ -685,11 +687,12 @@ def test_timing_stats():
 # ------------------------------------------------------------- full size ----
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_headline_256_parity(prec):
-    """256^3, 1000 grains with gradients: the benchmark workload, whole-field oracle."""
+def test_headline_256_parity(prec, bench_tuning):
+    """256^3, 1000 grains with gradients: the benchmark workload in the launch configuration the
+    benchmark times (the committed tuning), whole-field oracle."""
     say("headline 256", prec)
     S = wl.config_field("headline", dtype=np.float32 if prec == "fp32" else np.float64)
-    got, rem = run_project(S, "ddo", prec)
+    got, rem = run_project(S, "ddo", prec, tuning=bench_tuning)
     ref, _ = O.project(S.astype(np.float64), "ddo")
     err = rel_l2(got, ref)
     say("headline rel-L2", prec, err, "max-abs", float(np.abs(got - ref).max()))
