@@ -3,6 +3,8 @@
 the oracle, and the budget holds while requests queue and overlap.  The small classes
 run many requests; the serving workload's own classes 96^3 to 384^3 each run alone and
 in a mix with the others, and each class is checked against the oracle once."""
+import os
+
 import numpy as np
 import pytest
 
@@ -11,6 +13,7 @@ from paper_2105_01612_amd import workload as wl
 
 pytestmark = pytest.mark.gpu
 W6 = np.array([1, 1, 1, 2, 2, 2.0]).reshape(6, 1, 1, 1)
+TUNE_FILE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles", "tune_mi355x.json")
 
 
 def frob_rel(got, ref):
@@ -29,11 +32,11 @@ def _pools(sizes, per_class, grains_of):
     return host, pools
 
 
-def _alone(pools, budget, r):
+def _alone(pools, budget, r, tune_cache=None):
     from paper_2105_01612_amd.serve import GpuBackend, Request, Server
 
     out = {}
-    s1 = Server(GpuBackend(pools, prec="fp32", op="ddo"), budget)
+    s1 = Server(GpuBackend(pools, prec="fp32", op="ddo", tune_cache=tune_cache), budget)
     s1.run([Request(r.rid, r.n, 0.0, r.field)], on_complete=lambda q, o: out.__setitem__(q.rid, o.cpu().numpy().copy()))
     s1.close()
     return out[r.rid]
@@ -63,14 +66,24 @@ def test_alone_equals_mix_and_oracle():
 
 def test_serving_classes_alone_equal_mix_and_oracle():
     """The serving workload's classes 96, 128, 192, 256 and 384 (one grain per 16^3 voxels is
-    not needed for this check: a few grains per field), all requests arriving together so
-    that they overlap on the device, against each request alone and against the oracle."""
+    not needed for this check: a few grains per field), with the committed tuning as the
+    serving benchmark runs them, all requests arriving together so that they overlap on the
+    device, against each request alone and against the oracle."""
     import torch
     from paper_2105_01612_amd.serve import GpuBackend, Request, Server
 
+    import types
+
+    from paper_2105_01612_amd.autotune import cache_key, load_cache
+
     sizes = (96, 128, 192, 256, 384)
+    # the classes run with the committed tuning, as the serving benchmark runs them
+    entries = load_cache(TUNE_FILE)
+    for n in sizes:
+        key = cache_key(types.SimpleNamespace(nx=n, ny=n, nz=n, batch=1, prec="fp32", op="ddo"))
+        assert key in entries, f"{TUNE_FILE} holds no entry for the {n}^3 serving class"
     host, pools = _pools(sizes, 1, lambda n: 24)
-    be = GpuBackend(pools, prec="fp32", op="ddo")
+    be = GpuBackend(pools, prec="fp32", op="ddo", tune_cache=TUNE_FILE)
     budget = sum(be.slot_bytes(n) for n in sizes)
     order = [384, 96, 256, 128, 192, 96, 384, 128]
     reqs = [Request(i, n, 0.0, 0) for i, n in enumerate(order)]
@@ -87,7 +100,7 @@ def test_serving_classes_alone_equal_mix_and_oracle():
             assert np.array_equal(mix[r.rid], mix[next(q.rid for q in reqs if q.n == r.n)])
             continue
         seen.add(r.n)
-        assert np.array_equal(_alone(pools, budget, r), mix[r.rid]), r.n
+        assert np.array_equal(_alone(pools, budget, r, TUNE_FILE), mix[r.rid]), r.n
         ref, _ = O.project(host[r.n][0].astype(np.float64), "ddo")
         assert frob_rel(mix[r.rid], ref) <= 1e-5, r.n
         del ref
