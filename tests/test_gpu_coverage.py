@@ -7,7 +7,7 @@ the FP64 oracle:
   slabs reach every kernel those edges select: the 384 = 8 * 8 * 2 * 3 schedule and the
   192 = 8 * 8 * 3 one, on the line kernels of every axis);
 * every field of the 64 x 128^3 batch;
-* repeated in-loop projection x <- P(x) by graph replay;
+* repeated in-loop projection x <- P(x), by graph replay and by launching the passes;
 * an autotuned plan, and a cached plan reused without trial launches.
 
 Bars (the oracle's FP64 result on the same input bytes): Frobenius rel-L2 <= 1e-5 FP32,
@@ -147,11 +147,13 @@ def test_batched_64x128_every_field_against_oracle(bench_tuning):
 
 # ------------------------------------------------- in-loop graph replay -----
 
+@pytest.mark.parametrize("launch", ["graph", "stream"])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("n", [32, 64])
-def test_inloop_graph_replay_matches_oracle(prec, n):
-    """x <- P(x) between two buffers, k graph replays of one plan (32^3: five passes, 64^3:
-    three), with eager work and synchronizations between replays.  P is idempotent, so the
+def test_inloop_projection_matches_oracle(prec, n, launch, bench_tuning):
+    """x <- P(x) between two buffers, k calls of one plan (32^3: five passes, 64^3: three), each
+    replaying the captured graph or launching the passes, with the committed tuning as the in-loop
+    benchmark runs it, and eager work and synchronizations between calls.  P is idempotent, so the
     final buffer is compared with the oracle's P(x0) element by element."""
     import torch
     import paper_2105_01612_amd as eq
@@ -164,7 +166,8 @@ def test_inloop_graph_replay_matches_oracle(prec, n):
     dt = torch.float64 if prec == "fp64" else torch.float32
     k = 10
     with torch.cuda.stream(s):
-        plan = eq.plan(n, op="ddo", prec=prec, flags=["capture_graph"], stream=s)
+        plan = eq.plan(n, op="ddo", prec=prec, flags=["capture_graph"] if launch == "graph" else [], stream=s)
+        bench_tuning(plan, required=(n, prec) == (64, "fp32"))
         a = torch.from_numpy(S).to(device="cuda", dtype=dt)
         b = torch.empty_like(a)
         for i in range(k // 2):
@@ -176,7 +179,7 @@ def test_inloop_graph_replay_matches_oracle(prec, n):
         got = a.double().cpu().numpy()
         plan.destroy()
     err = rel_l2(got, ref)
-    say("  inloop", n, prec, "rel-L2 after", k, "projections", err)
+    say("  inloop", n, prec, launch, "rel-L2 after", k, "projections", err)
     assert err <= TOL[prec]
 
 
