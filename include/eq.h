@@ -214,8 +214,8 @@ eq_status eq_plan_reset_stats(eq_plan_t p);
  *            reported as 4 or 8 on the three-pass route (4 under EQ_F_PERSISTENT), else 0.
  * Invalid shapes for this grid return EQ_ERR_ARG (EQ_ERR_SIZE if LDS would exceed the device
  * limit) and leave the plan unchanged.  Every setting computes the same transform; results
- * may differ only by floating-point rounding order where radix16, radix4, zp_e or schedule
- * changes the radix stages or the pass order (launch shapes alone give the same bits).
+ * may differ only by floating-point rounding order (radix16, radix4, zp_e and schedule change
+ * the radix stages or the pass order; the other knobs can change which kernel serves a pass).
  * The EQ_TUNE environment variable ("tx_y=16,tx_z=32,rw_x=4,chunk=32,radix16=2,schedule=5") seeds the
  * tuning at eq_plan.  eq_plan_get_tune reports the settings in effect (defaults resolved). */
 typedef struct { int tx_y, tx_z, rw_x, chunk, radix16, schedule, tc_zp, radix4, xsplit, zp_e; } eq_tune;
