@@ -275,7 +275,12 @@ def test_xsplit_parity(prec, op, shape, radix, P):
     torch = torch_mod()
     nz, ny, nx = shape
     if "radix4" in radix and prec == "fp64":
-        pytest.skip("radix-4 x stages are FP32 only")
+        # radix-4 x stages exist in FP32 only: an FP64 plan accepts the knob and reports it off
+        plan = eq.plan(nx, ny, nz, op=op, prec=prec)
+        plan.tune(schedule=5, radix4=1)
+        assert plan.get_tune()["radix4"] == 0
+        plan.destroy()
+        return
     say("xsplit", prec, op, shape, radix)
     h = 0.7
     S = wl.voronoi_field(wl.FieldSpec(shape, grains=6, sigma_grain=80.0, sigma_noise=4.0, sigma_grad=1.0,
