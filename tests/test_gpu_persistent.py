@@ -163,3 +163,31 @@ def test_persistent_wait_that_gives_up_is_reported(monkeypatch):
     ok.project(x, out)
     ok.residual(out)
     ok.destroy()
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (256, 64, 64), (128, 128, 128)])
+@pytest.mark.parametrize("b", [1, 7, 8, 13])
+def test_persistent_batch_counts_around_the_item_size_switch(shape, b):
+    """Batches of 1, 7, 8 and 13 fields (items grow fourfold from eight fields on, and the queue's
+    last step is partly empty for odd counts): bitwise equal to the per-pass three-pass schedule
+    with the same z stage, with the removed part, both on the first call and on a repeated one."""
+    import torch
+    import paper_2105_01612_amd as eq
+
+    nz, ny, nx = shape
+    say("persistent batch count", shape, b)
+    S = batch(shape, b, 1300 + b + nz, grains=10)
+    x = torch.from_numpy(S).cuda()
+    per = eq.plan(nx, ny, nz, batch=b, op="ddo", prec="fp32")
+    per.tune(schedule=3, zp_e=4)
+    ref, ref_rem = torch.empty_like(x), torch.empty_like(x)
+    per.project(x, ref, ref_rem)
+    ps = eq.plan(nx, ny, nz, batch=b, op="ddo", prec="fp32", flags=["persistent"])
+    for call in range(2):
+        out, rem = torch.full_like(x, float("nan")), torch.full_like(x, float("nan"))
+        ps.project(x, out, rem)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref) and torch.equal(rem, ref_rem), call
+    ps.residual(out)                         # reports a dependency wait that gave up
+    per.destroy()
+    ps.destroy()
