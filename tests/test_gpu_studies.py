@@ -8,19 +8,27 @@ from paper_2105_01612_amd import workload as wl
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("case", [((32, 32, 32), 20, 1, "fp64"),
+                                  ((64, 64, 64), 100, 64, "fp64"),     # the paper's cell (Section 5.1)
+                                  ((64, 64, 64), 100, 64, "fp32")])
 @pytest.mark.parametrize("op", ["cdo", "ddo"])
-def test_grain_average_recovery_matches_oracle(op):
+def test_grain_average_recovery_matches_oracle(op, case):
     from paper_2105_01612_amd.studies import frobenius, grain_average_recovery
 
-    spec = wl.FieldSpec((32, 32, 32), grains=20, sigma_grain=100.0, sigma_noise=5.0, seed=1)
-    r = grain_average_recovery(spec, op=op, prec="fp64", keep_fields=True)
-    T_ref, _ = O.project(wl.voronoi_field(spec), op)
+    shape, grains, seed, prec = case
+    spec = wl.FieldSpec(shape, grains=grains, sigma_grain=100.0, sigma_noise=5.0, seed=seed)
+    r = grain_average_recovery(spec, op=op, prec=prec, keep_fields=True)
+    S0 = wl.voronoi_field(spec)
+    if prec == "fp32":                        # the study projects the FP32 rounding of the field
+        S0 = S0.astype(np.float32).astype(np.float64)
+    T_ref, _ = O.project(S0, op)
     A_ref = wl.grain_average(T_ref, wl.grain_labels(spec), spec.grains)
     R_ref, _ = O.project(A_ref, op)
     f = r["fields"]
-    assert frobenius(f["T"] - T_ref) <= 1e-12 * frobenius(T_ref)
-    assert frobenius(f["R"] - R_ref) <= 1e-12 * frobenius(R_ref)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert frobenius(f["T"] - T_ref) <= tol * frobenius(T_ref)
+    assert frobenius(f["R"] - R_ref) <= tol * frobenius(R_ref)
     # the filter removes the symmetric-gradient part of the averaging error only
-    assert r["pythagoras_rel_gap"] <= 1e-10
+    assert r["pythagoras_rel_gap"] <= (1e-10 if prec == "fp64" else 1e-5)
     assert r["recovered_vs_truth"]["rel_l2"] < r["average_vs_truth"]["rel_l2"]
-    assert r["residual_rel_truth"] <= 1e-13
+    assert r["residual_rel_truth"] <= (1e-13 if prec == "fp64" else 2e-6)
